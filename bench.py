@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""FP64 GEMM benchmark on one MI355X: native dgemm sweep through the C ABI.
+
+One step = one pass over the sweep workload: the four (transa, transb) cases of
+square m = n = k in {1024, 2048, 4096, 4099, 8192, 16384} and the skinny
+m = n = 8192, k = 64 (28 GEMMs), ld = stored rows rounded up to a multiple of 8,
+alpha = beta = 1, Uniform[-1,1] entries drawn by the seeded generator and
+resident in HBM before timing starts. value = total 2mnk flops / timed seconds.
+
+Prints ONE JSON line (rank 0). Only one GPU is supported: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64 GEMM TFLOP/s (% of MFMA peak), native vs split-precision at err<=1e-13"
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+SQUARES = [1024, 2048, 4096, 4099, 8192, 16384]
+SKINNY = (8192, 8192, 64)
+TRANS = ["NN", "NT", "TN", "TT"]
+SOURCE = os.path.join(ROOT, "paper_1609_00076_amd", "csrc", "mdg_dgemm.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    return hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()[:16]
+
+
+def build_problems(torch, shapes_filter=None):
+    """Seeded host operands for the sweep and their device copies (square sizes share A, B, C
+    across the four transpose cases). Returns a list of problems with host arrays hA, hB, hC and
+    device tensors A, B, C."""
+    import synth
+    probs = []
+    for size in SQUARES:
+        if shapes_filter and size not in shapes_filter:
+            continue
+        ld = synth.ld_round8(size)
+        hA = synth.matrix(synth.seed_for(2, 100, 0), size, size, ld)
+        hB = synth.matrix(synth.seed_for(2, 100, 1), size, size, ld)
+        hC = synth.matrix(synth.seed_for(2, 100, 2), size, size, ld, pad=synth.pad_c_value())
+        A, B, C = (torch.from_numpy(x).cuda() for x in (hA, hB, hC))
+        for tr in TRANS:
+            probs.append(dict(transa=tr[0], transb=tr[1], m=size, n=size, k=size, A=A, lda=ld,
+                              B=B, ldb=ld, C=C, ldc=ld, hA=hA, hB=hB, hC=hC))
+        log(f"[bench] operands for {size}^3 resident")
+    if not shapes_filter or "skinny" in shapes_filter:
+        m, n, k = SKINNY
+        ldc = synth.ld_round8(m)
+        hC = synth.matrix(synth.seed_for(2, 101, 2), m, n, ldc, pad=synth.pad_c_value())
+        C = torch.from_numpy(hC).cuda()
+        for t, tr in enumerate(TRANS):
+            ra, ca = synth.stored_dims(tr[0], m, k)
+            rb, cb = synth.stored_dims(tr[1], k, n)
+            lda, ldb = synth.ld_round8(ra), synth.ld_round8(rb)
+            hA = synth.matrix(synth.seed_for(2, 110 + t, 0), ra, ca, lda)
+            hB = synth.matrix(synth.seed_for(2, 110 + t, 1), rb, cb, ldb)
+            A, B = torch.from_numpy(hA).cuda(), torch.from_numpy(hB).cuda()
+            probs.append(dict(transa=tr[0], transb=tr[1], m=m, n=n, k=k, A=A, lda=lda, B=B,
+                              ldb=ldb, C=C, ldc=ldc, hA=hA, hB=hB, hC=hC))
+        log("[bench] operands for 8192x8192x64 resident")
+    return probs
+
+
+def flops(p):
+    return 2.0 * p["m"] * p["n"] * p["k"]
+
+
+def hbm_bytes(p, beta=1.0):
+    """Algorithmic bytes: read op(A), op(B) once, read C if beta != 0, write C once."""
+    m, n, k = p["m"], p["n"], p["k"]
+    return 8.0 * (m * k + k * n + m * n * (beta != 0.0) + m * n)
+
+
+def kernel_key(mdg, p):
+    v = mdg.mdg_select_variant(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, 1.0)
+    return f"{mdg.mdg_variant_name(v)}[{p['transa']}{p['transb']}]"
+
+
+def run_step(mdg, probs, events=None):
+    for i, p in enumerate(probs):
+        if events is not None:
+            events[i][0].record()
+        st = mdg.mdg_dgemm(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, p["A"],
+                           p["lda"], p["B"], p["ldb"], 1.0, p["C"], p["ldc"])
+        if st:
+            raise RuntimeError(f"mdg_dgemm failed: {mdg.mdg_status_string(st)}")
+        if events is not None:
+            events[i][1].record()
+
+
+def cpu_baseline(probs, budget_s: float):
+    """Time the CPU oracle on blocks of the sweep problems, on the host copies of the inputs.
+
+    Each problem gets an equal share of the budget. Within it the oracle computes
+    consecutive r x c blocks of C (c = one column per thread, r starting at 16 rows and
+    doubling while a call takes under a quarter of the share), walking down the leading
+    columns, on the problem's own arrays with pointer offsets (no data movement; the
+    results go to a scratch C). Returns (TFLOP/s, threads, description).
+    """
+    import numpy as np
+
+    import oracle
+    threads = oracle.get_threads()
+    share = budget_s / len(probs)
+    total_flops, total_t, entries = 0.0, 0.0, 0
+    for p in probs:
+        m, n, k = p["m"], p["n"], p["k"]
+        ta, tb, lda, ldb = p["transa"], p["transb"], p["lda"], p["ldb"]
+        hA, hB = p["hA"], p["hB"]
+        C = np.zeros(m * threads)
+        spent, i0, j0, r = 0.0, 0, 0, min(16, m)
+        while spent < share and j0 < n:
+            rr, c = min(r, m - i0), min(threads, n - j0)
+            aoff = i0 if ta == "N" else i0 * lda   # rows i0.. of op(A)
+            boff = j0 * ldb if tb == "N" else j0   # columns j0.. of op(B)
+            t0 = time.perf_counter()
+            st = oracle.dgemm(ta, tb, rr, c, k, 1.0, hA[aoff:], lda, hB[boff:], ldb, 1.0, C, m)
+            dt = time.perf_counter() - t0
+            assert st == 0
+            spent += dt
+            total_t += dt
+            total_flops += 2.0 * rr * c * k
+            entries += rr * c
+            i0 += rr
+            if i0 >= m:
+                i0, j0 = 0, j0 + c
+            if dt < share / 4:
+                r *= 2
+    desc = (f"oracle on leading blocks of C of each of the {len(probs)} sweep GEMMs "
+            f"({entries} entries of C, {total_t:.1f} s, one column per thread per call)")
+    return total_flops / total_t / 1e12, threads, desc
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of CPU time for the oracle baseline (0 disables it)")
+    ap.add_argument("--shapes", default="", help="comma list of sizes and/or 'skinny' (default: all)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1609_00076_amd as mdg
+    mdg.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device visible", file=sys.stderr)
+        sys.exit(1)
+
+    shapes_filter = None
+    if args.shapes:
+        shapes_filter = {int(s) if s.isdigit() else s for s in args.shapes.split(",")}
+    probs = build_problems(torch, shapes_filter)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        run_step(mdg, probs)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {w + 1}/{args.warmup} done")
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in probs] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for s in range(args.steps):
+        run_step(mdg, probs, ev[s])
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    log(f"[bench] {args.steps} timed steps done in {total_ms:.1f} ms")
+
+    step_flops = sum(flops(p) for p in probs)
+    value = step_flops * args.steps / (total_ms * 1e-3) / 1e12
+
+    # per-kernel and per-problem launch times from the per-call events
+    per_kernel = {}
+    per_problem = {}
+    for s in range(args.steps):
+        for i, p in enumerate(probs):
+            ms = ev[s][i][0].elapsed_time(ev[s][i][1])
+            key = kernel_key(mdg, p)
+            d = per_kernel.setdefault(key, dict(ms=0.0, flops=0.0, bytes=0.0, launches=0))
+            d["ms"] += ms
+            d["flops"] += flops(p)
+            d["bytes"] += hbm_bytes(p)
+            d["launches"] += 1
+            name = f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}"
+            per_problem.setdefault(name, []).append(ms)
+    dom_key = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
+    dom = per_kernel[dom_key]
+    avg_ms = dom["ms"] / dom["launches"]
+    achieved = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            t = json.load(open(TRAFFIC_FILE))
+            if t.get("source_sha") == source_hash() and t.get("kernel") == dom_key:
+                traffic = t.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    breakdown = {}
+    for name, times in per_problem.items():
+        m, n, k = (int(x) for x in name.split()[1].split("x"))
+        med = sorted(times)[len(times) // 2]
+        breakdown[name] = round(2.0 * m * n * k / (med * 1e-3) / 1e12, 2)
+
+    cpu = None
+    if args.cpu_budget > 0:
+        log("[bench] timing the CPU oracle baseline")
+        v, cores, desc = cpu_baseline(probs, args.cpu_budget)
+        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "pct_of_peak": round(100.0 * value / PEAK_FP64_MFMA_TFLOPS, 1),
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded Uniform[-1,1] FP64, resident in HBM before timing",
+        "config": {
+            "workload": "native dgemm sweep: (N|T)x(N|T) x square m=n=k in "
+                        "{1024,2048,4096,4099,8192,16384} + 8192x8192x64; ld = stored rows rounded "
+                        "up to a multiple of 8; alpha=beta=1" if not shapes_filter else
+                        f"native dgemm subset {sorted(map(str, shapes_filter))}",
+            "gemms_per_step": len(probs),
+            "flops_per_step": step_flops,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": dom_key,
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
+            "avg_launch_ms": round(avg_ms, 4),
+            "launches": dom["launches"],
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+        "per_problem_tflops": breakdown,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

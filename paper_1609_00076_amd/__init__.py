@@ -1,0 +1,14 @@
+"""MI355X-native double-precision GEMM (dgemm) with hand-written gfx950 HIP kernels.
+
+C := alpha*op(A)*op(B) + beta*C on column-major operands with leading
+dimensions, exported by libmdg.so through the C ABI in include/mdg.h. This
+package is the thin Python binding (ctypes); torch supplies device memory and
+streams only.
+"""
+from .binding import (MdgError, dgemm, load, mdg_dgemm, mdg_dgemm_ex, mdg_num_variants,
+                      mdg_select_variant, mdg_status_string, mdg_variant_info, mdg_variant_name,
+                      mdg_version)
+
+__all__ = ["MdgError", "dgemm", "load", "mdg_dgemm", "mdg_dgemm_ex", "mdg_num_variants",
+           "mdg_select_variant", "mdg_status_string", "mdg_variant_info", "mdg_variant_name",
+           "mdg_version"]

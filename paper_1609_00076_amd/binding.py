@@ -1,0 +1,170 @@
+"""Thin ctypes binding of libmdg.so (include/mdg.h); argument marshalling only.
+
+Each ``mdg_*`` function here has the name, argument order and return code of
+the C entry point of the same name. Matrix arguments may be torch tensors
+(float64, on the HIP device; the pointer passed is ``data_ptr()``), raw device
+addresses as ints, or None (NULL). For tensors the binding also checks, before
+the call, that the storage from ``data_ptr()`` onward covers every element the
+call may touch, so that a caller's mistake becomes an exception instead of an
+out-of-bounds access on the GPU. All computation happens in the HIP kernels;
+there is no fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import LIB_PATH
+
+_lib = None
+
+
+class MdgError(RuntimeError):
+    def __init__(self, status: int):
+        self.status = status
+        super().__init__(f"mdg status {status}: {mdg_status_string(status)}")
+
+
+def load():
+    """Open libmdg.so (built in-tree by paper_1609_00076_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1609_00076_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, dbl, vp, ch, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char, ctypes.c_int
+    gemm_args = [ch, ch, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp]
+    lib.mdg_dgemm.argtypes = gemm_args
+    lib.mdg_dgemm.restype = ci
+    lib.mdg_dgemm_ex.argtypes = [ci] + gemm_args
+    lib.mdg_dgemm_ex.restype = ci
+    lib.mdg_select_variant.argtypes = [ch, ch, i64, i64, i64, dbl, dbl]
+    lib.mdg_select_variant.restype = ci
+    lib.mdg_num_variants.argtypes = []
+    lib.mdg_num_variants.restype = ci
+    lib.mdg_variant_name.argtypes = [ci]
+    lib.mdg_variant_name.restype = ctypes.c_char_p
+    lib.mdg_variant_info.argtypes = [ci] + [ctypes.POINTER(ci)] * 4
+    lib.mdg_variant_info.restype = ci
+    lib.mdg_status_string.argtypes = [ci]
+    lib.mdg_status_string.restype = ctypes.c_char_p
+    lib.mdg_version.argtypes = []
+    lib.mdg_version.restype = ci
+    _lib = lib
+    return lib
+
+
+def _ch(t) -> bytes:
+    if isinstance(t, bytes):
+        return t[:1]
+    if isinstance(t, str) and len(t) == 1:
+        return t.encode()
+    return b"\0"  # rejected by the library's argument check
+
+
+def _is_trans(t) -> bool:
+    return _ch(t) in (b"T", b"t", b"C", b"c")
+
+
+def _extent(rows: int, cols: int, ld: int) -> int:
+    """Elements from the first one to the last one of a rows x cols column-major matrix."""
+    return 0 if rows <= 0 or cols <= 0 else (cols - 1) * ld + rows
+
+
+def _ptr(x, need: int, name: str):
+    """Device address of x; for tensors, also check dtype, device and storage extent."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, an int address or None")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name}: dtype must be float64, got {x.dtype}")
+    if x.device.type != "cuda":
+        raise TypeError(f"{name}: tensor must be on the HIP device, got {x.device}")
+    if need > 0:
+        st = x.untyped_storage()
+        avail = (st.data_ptr() + st.nbytes() - x.data_ptr()) // 8
+        if avail < need:
+            raise ValueError(f"{name}: storage holds {avail} doubles past data_ptr(), call needs {need}")
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # a torch.cuda.Stream
+
+
+def _marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream):
+    empty = m <= 0 or n <= 0
+    reads_ab = not empty and alpha != 0.0 and k > 0
+    touches_c = not empty and not ((alpha == 0.0 or k <= 0) and beta == 1.0)
+    ra, ca = (k, m) if _is_trans(transa) else (m, k)
+    rb, cb = (n, k) if _is_trans(transb) else (k, n)
+    need_a = _extent(ra, ca, lda) if reads_ab and lda >= max(1, ra) else 0
+    need_b = _extent(rb, cb, ldb) if reads_ab and ldb >= max(1, rb) else 0
+    need_c = _extent(m, n, ldc) if touches_c and ldc >= max(1, m) else 0
+    return (_ch(transa), _ch(transb), int(m), int(n), int(k), float(alpha),
+            _ptr(A, need_a, "A"), int(lda), _ptr(B, need_b, "B"), int(ldb), float(beta),
+            _ptr(C, need_c, "C"), int(ldc), _stream(stream) if touches_c else None)
+
+
+def mdg_dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None) -> int:
+    """C := alpha*op(A)*op(B) + beta*C; returns the library's status code."""
+    return load().mdg_dgemm(*_marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                                      ldc, stream))
+
+
+def mdg_dgemm_ex(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                 stream=None) -> int:
+    """mdg_dgemm with an explicit kernel variant (or -1 for automatic choice)."""
+    return load().mdg_dgemm_ex(int(variant), *_marshal(transa, transb, m, n, k, alpha, A, lda, B,
+                                                       ldb, beta, C, ldc, stream))
+
+
+def mdg_select_variant(transa, transb, m, n, k, alpha, beta) -> int:
+    return load().mdg_select_variant(_ch(transa), _ch(transb), int(m), int(n), int(k),
+                                     float(alpha), float(beta))
+
+
+def mdg_num_variants() -> int:
+    return load().mdg_num_variants()
+
+
+def mdg_variant_name(variant: int):
+    s = load().mdg_variant_name(int(variant))
+    return None if s is None else s.decode()
+
+
+def mdg_variant_info(variant: int):
+    """(mt, nt, kt, threads) of a variant; raises MdgError for an unknown id."""
+    vals = [ctypes.c_int() for _ in range(4)]
+    st = load().mdg_variant_info(int(variant), *[ctypes.byref(v) for v in vals])
+    if st:
+        raise MdgError(st)
+    return tuple(v.value for v in vals)
+
+
+def mdg_status_string(status: int) -> str:
+    return load().mdg_status_string(int(status)).decode()
+
+
+def mdg_version() -> int:
+    return load().mdg_version()
+
+
+def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None, variant=-1):
+    """mdg_dgemm_ex that raises MdgError on a non-zero status."""
+    st = mdg_dgemm_ex(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
+    if st:
+        raise MdgError(st)

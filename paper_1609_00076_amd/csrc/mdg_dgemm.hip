@@ -1,0 +1,417 @@
+// mdg_dgemm.hip -- FP64 GEMM on the MI355X (gfx950) matrix cores, behind the C ABI of include/mdg.h.
+//
+// Operation (paper, section 1.2): C := alpha*op(A)*op(B) + beta*C, column-major with leading
+// dimensions (paper, section 2.3). The paper's blocked algorithm (section 4.1: the five loops
+// around a micro-kernel, with packing into contiguous panels) is realised for a GPU as:
+//   loops 5 and 3 (jc, ic)   -> the grid: one workgroup per mt x nt macro-tile of C;
+//   loop 4 (pc) and packing  -> a loop over kt-deep k-panels; each panel of op(A) (mt x kt) and
+//                               op(B) (kt x nt) is staged from HBM into LDS, transposed on the way
+//                               when the operand is stored the other way round;
+//   loops 2 and 1 (jr, ir)   -> the waves of a workgroup, each owning a wm x wn sub-tile;
+//   loop 0 (the micro-kernel)-> chains of v_mfma_f64_16x16x4_f64, each one four rank-1 updates of a
+//                               16x16 block held in accumulator registers (section 4.3).
+// Fringes (section 2.4: m, n, k not multiples of the block sizes) are handled in the kernel: loads
+// outside the logical matrix read a clamped in-bounds address and are replaced by zero, and stores
+// outside C are masked, so the padding rows of every operand are never read or written.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "mdg.h"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kVersion = 100;  // 0.1.0
+
+struct GemmArgs {
+  int64_t m, n, k;
+  int64_t lda, ldb, ldc;
+  double alpha, beta;
+  const double* A;
+  const double* B;
+  double* C;
+};
+
+// ------------------------------------------------------------------------------------------------
+// Tile configuration. MT x NT macro-tile per workgroup, KT-deep k-panels, WM x WN per wave.
+// ------------------------------------------------------------------------------------------------
+template <int MT_, int NT_, int KT_, int WM_, int WN_>
+struct Cfg {
+  static constexpr int MT = MT_, NT = NT_, KT = KT_, WM = WM_, WN = WN_;
+  static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
+  static constexpr int WAVES = WAVES_M * WAVES_N;
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int BM = WM / 16, BN = WN / 16;  // 16x16 MFMA blocks per wave
+  // LDS rows are k-major: panel element (row r, k-index q) sits at q*LDS_A + r. Two extra doubles
+  // per row shift consecutive k-rows across banks.
+  static constexpr int LDS_A = MT + 2, LDS_B = NT + 2;
+  static constexpr int A_PER_THREAD = MT * KT / THREADS;
+  static constexpr int B_PER_THREAD = KT * NT / THREADS;
+  static_assert(MT % WM == 0 && NT % WN == 0, "wave grid");
+  static_assert(WM % 16 == 0 && WN % 16 == 0 && KT % 4 == 0, "MFMA shape");
+  static_assert((MT * KT) % THREADS == 0 && (KT * NT) % THREADS == 0, "panel split");
+};
+
+// XCD-aware tile order. Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
+// its own L2; the remap gives each XCD a contiguous run of tiles, and within a run tiles are
+// visited in column groups of GROUP tile-rows so that co-resident workgroups share A and B panels.
+__device__ __forceinline__ void tile_coords(int wg, int nwg, int tiles_m, int tiles_n, int& tm,
+                                            int& tn) {
+  constexpr int XCDS = 8, GROUP = 8;
+  int t = wg;
+  if (nwg % XCDS == 0) t = (wg % XCDS) * (nwg / XCDS) + wg / XCDS;
+  int per_group = GROUP * tiles_n;
+  int g = t / per_group;
+  int first_m = g * GROUP;
+  int gsize = min(tiles_m - first_m, GROUP);
+  int r = t - g * per_group;
+  tm = first_m + r % gsize;
+  tn = r / gsize;
+}
+
+// Load this thread's share of the op(A) panel (rows row0.., k-indices k0..) into registers.
+// TA == false: A is stored m x k (contiguous along m); consecutive threads take consecutive rows.
+// TA == true : A is stored k x m (contiguous along k); consecutive threads take consecutive k.
+template <class C, bool TA>
+__device__ __forceinline__ void load_a(const GemmArgs& g, int64_t row0, int64_t k0, int tid,
+                                       double (&ra)[C::A_PER_THREAD]) {
+#pragma unroll
+  for (int r = 0; r < C::A_PER_THREAD; ++r) {
+    int e = tid + r * C::THREADS;
+    int i, q;
+    if (TA) { q = e % C::KT; i = e / C::KT; }
+    else    { i = e % C::MT; q = e / C::MT; }
+    int64_t gi = row0 + i, gq = k0 + q;
+    bool ok = gi < g.m && gq < g.k;
+    int64_t ci = ok ? gi : g.m - 1, cq = ok ? gq : g.k - 1;
+    double v = TA ? g.A[ci * g.lda + cq] : g.A[cq * g.lda + ci];
+    ra[r] = ok ? v : 0.0;
+  }
+}
+
+template <class C, bool TA>
+__device__ __forceinline__ void store_a(double* As, int tid, const double (&ra)[C::A_PER_THREAD]) {
+#pragma unroll
+  for (int r = 0; r < C::A_PER_THREAD; ++r) {
+    int e = tid + r * C::THREADS;
+    int i, q;
+    if (TA) { q = e % C::KT; i = e / C::KT; }
+    else    { i = e % C::MT; q = e / C::MT; }
+    As[q * C::LDS_A + i] = ra[r];
+  }
+}
+
+// op(B) panel: TB == false: B stored k x n (contiguous along k); TB == true: n x k (along n).
+template <class C, bool TB>
+__device__ __forceinline__ void load_b(const GemmArgs& g, int64_t col0, int64_t k0, int tid,
+                                       double (&rb)[C::B_PER_THREAD]) {
+#pragma unroll
+  for (int r = 0; r < C::B_PER_THREAD; ++r) {
+    int e = tid + r * C::THREADS;
+    int j, q;
+    if (TB) { j = e % C::NT; q = e / C::NT; }
+    else    { q = e % C::KT; j = e / C::KT; }
+    int64_t gj = col0 + j, gq = k0 + q;
+    bool ok = gj < g.n && gq < g.k;
+    int64_t cj = ok ? gj : g.n - 1, cq = ok ? gq : g.k - 1;
+    double v = TB ? g.B[cq * g.ldb + cj] : g.B[cj * g.ldb + cq];
+    rb[r] = ok ? v : 0.0;
+  }
+}
+
+template <class C, bool TB>
+__device__ __forceinline__ void store_b(double* Bs, int tid, const double (&rb)[C::B_PER_THREAD]) {
+#pragma unroll
+  for (int r = 0; r < C::B_PER_THREAD; ++r) {
+    int e = tid + r * C::THREADS;
+    int j, q;
+    if (TB) { j = e % C::NT; q = e / C::NT; }
+    else    { q = e % C::KT; j = e / C::KT; }
+    Bs[q * C::LDS_B + j] = rb[r];
+  }
+}
+
+// One workgroup computes one MT x NT tile of C.
+//
+// MFMA operand roles: v_mfma_f64_16x16x4_f64(X, Y, Z) forms D = X*Y + Z for a 16x4 X and a 4x16
+// Y, where lane l supplies X[l%16][l/16] and Y[l/16][l%16] and holds D[l/16 + 4r][l%16] in its
+// r-th accumulator. Feeding X = op(B)^T and Y = op(A)^T makes D = C^T, so lane l holds
+// C(i0 + l%16, j0 + l/16 + 4r): lanes 0..15 of each accumulator register cover 16 consecutive
+// rows of one column of C, which makes the epilogue's loads and stores of column-major C
+// contiguous 128-byte runs.
+template <class C, bool TA, bool TB>
+__global__ void __launch_bounds__(C::THREADS)
+dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  __shared__ double As[2][C::KT * C::LDS_A];
+  __shared__ double Bs[2][C::KT * C::LDS_B];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wave_m = wave % C::WAVES_M;
+  const int wave_n = wave / C::WAVES_M;
+
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  const int64_t row0 = (int64_t)tm * C::MT;
+  const int64_t col0 = (int64_t)tn * C::NT;
+
+  d4 acc[C::BM][C::BN];
+#pragma unroll
+  for (int bi = 0; bi < C::BM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < C::BN; ++bj) acc[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  double ra[C::A_PER_THREAD], rb[C::B_PER_THREAD];
+  const int64_t num_k = (g.k + C::KT - 1) / C::KT;
+
+  load_a<C, TA>(g, row0, 0, tid, ra);
+  load_b<C, TB>(g, col0, 0, tid, rb);
+  store_a<C, TA>(As[0], tid, ra);
+  store_b<C, TB>(Bs[0], tid, rb);
+  __syncthreads();
+
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int a_off = wave_m * C::WM + l16;  // row within the panel this lane feeds
+  const int b_off = wave_n * C::WN + l16;  // column within the panel this lane feeds
+
+  for (int64_t kt = 0; kt < num_k; ++kt) {
+    const int buf = kt & 1;
+    const bool more = kt + 1 < num_k;
+    if (more) {
+      load_a<C, TA>(g, row0, (kt + 1) * C::KT, tid, ra);
+      load_b<C, TB>(g, col0, (kt + 1) * C::KT, tid, rb);
+    }
+    const double* as = As[buf];
+    const double* bs = Bs[buf];
+#pragma unroll
+    for (int s = 0; s < C::KT / 4; ++s) {
+      const int q = 4 * s + lq;
+      double af[C::BM], bf[C::BN];
+#pragma unroll
+      for (int bi = 0; bi < C::BM; ++bi) af[bi] = as[q * C::LDS_A + a_off + 16 * bi];
+#pragma unroll
+      for (int bj = 0; bj < C::BN; ++bj) bf[bj] = bs[q * C::LDS_B + b_off + 16 * bj];
+#pragma unroll
+      for (int bi = 0; bi < C::BM; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < C::BN; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
+    }
+    if (more) {
+      store_a<C, TA>(As[buf ^ 1], tid, ra);
+      store_b<C, TB>(Bs[buf ^ 1], tid, rb);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int bi = 0; bi < C::BM; ++bi) {
+    const int64_t i = row0 + wave_m * C::WM + 16 * bi + l16;
+    if (i >= g.m) continue;
+#pragma unroll
+    for (int bj = 0; bj < C::BN; ++bj) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = col0 + wave_n * C::WN + 16 * bj + lq + 4 * r;
+        if (j < g.n) {
+          double* c = g.C + j * g.ldc + i;
+          double v = alpha * acc[bi][bj][r];
+          if (beta != 0.0) v += beta * *c;
+          *c = v;
+        }
+      }
+    }
+  }
+}
+
+// C := beta*C over the logical m x n matrix (beta == 0 writes zeros without reading C). This is
+// the whole operation when alpha == 0 or k == 0.
+__global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, double beta, double* C,
+                                                      int64_t ldc) {
+  const int64_t total = m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j = e / m, i = e - j * m;
+    double* c = C + j * ldc + i;
+    *c = (beta == 0.0) ? 0.0 : beta * *c;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Variant table.
+// ------------------------------------------------------------------------------------------------
+using Big = Cfg<128, 128, 16, 64, 64>;    // 4 waves, each 64x64 (16 MFMA chains)
+using Small = Cfg<64, 64, 16, 32, 32>;    // 4 waves, each 32x32 (4 MFMA chains)
+
+typedef void (*KernelFn)(GemmArgs, int, int);
+
+struct Variant {
+  const char* name;
+  int mt, nt, kt, threads;
+  KernelFn fn[2][2];  // [transa][transb]
+};
+
+template <class C>
+constexpr Variant make_variant(const char* name) {
+  return Variant{name,
+                 C::MT,
+                 C::NT,
+                 C::KT,
+                 C::THREADS,
+                 {{dgemm_mfma_kernel<C, false, false>, dgemm_mfma_kernel<C, false, true>},
+                  {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
+}
+
+const Variant kVariants[] = {
+    make_variant<Big>("mfma_f64_128x128x16_w64x64"),
+    make_variant<Small>("mfma_f64_64x64x16_w32x32"),
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+bool is_notrans(char t) { return t == 'N' || t == 'n'; }
+bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+int64_t max1(int64_t x) { return x > 1 ? x : 1; }
+
+// Argument checks in dgemm argument order; 0 or the 1-based position of the first bad argument.
+int check_args(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+               const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+               const double* C, int64_t ldc) {
+  if (!is_notrans(transa) && !is_trans(transa)) return 1;
+  if (!is_notrans(transb) && !is_trans(transb)) return 2;
+  if (m < 0) return 3;
+  if (n < 0) return 4;
+  if (k < 0) return 5;
+  const bool empty = (m == 0 || n == 0);
+  const bool reads_ab = !empty && alpha != 0.0 && k != 0;
+  const bool touches_c = !empty && !((alpha == 0.0 || k == 0) && beta == 1.0);
+  const int64_t rows_a = is_notrans(transa) ? m : k;
+  const int64_t rows_b = is_notrans(transb) ? k : n;
+  if (reads_ab && A == nullptr) return 7;
+  if (lda < max1(rows_a)) return 8;
+  if (reads_ab && B == nullptr) return 9;
+  if (ldb < max1(rows_b)) return 10;
+  if (touches_c && C == nullptr) return 12;
+  if (ldc < max1(m)) return 13;
+  return 0;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Shape heuristic: the large tile when it gives at least two tiles per CU (256 CUs), else the
+// small one, which quadruples the number of workgroups.
+int pick_variant(int64_t m, int64_t n, int64_t /*k*/) {
+  const int64_t big_tiles = ceil_div(m, 128) * ceil_div(n, 128);
+  return big_tiles >= 512 ? 0 : 1;
+}
+
+int device_check() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MDG_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MDG_ERR_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MDG_ERR_DEVICE;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdg_version(void) { return kVersion; }
+
+int mdg_num_variants(void) { return kNumVariants; }
+
+const char* mdg_variant_name(int variant) {
+  return (variant >= 0 && variant < kNumVariants) ? kVariants[variant].name : nullptr;
+}
+
+int mdg_variant_info(int variant, int* mt, int* nt, int* kt, int* threads) {
+  if (variant < 0 || variant >= kNumVariants) return MDG_ERR_VARIANT;
+  const Variant& v = kVariants[variant];
+  if (mt) *mt = v.mt;
+  if (nt) *nt = v.nt;
+  if (kt) *kt = v.kt;
+  if (threads) *threads = v.threads;
+  return 0;
+}
+
+const char* mdg_status_string(int status) {
+  switch (status) {
+    case MDG_SUCCESS: return "success";
+    case 1: return "invalid argument 1: transa is not one of N, n, T, t, C, c";
+    case 2: return "invalid argument 2: transb is not one of N, n, T, t, C, c";
+    case 3: return "invalid argument 3: m < 0";
+    case 4: return "invalid argument 4: n < 0";
+    case 5: return "invalid argument 5: k < 0";
+    case 7: return "invalid argument 7: A is NULL but would be read";
+    case 8: return "invalid argument 8: lda < max(1, rows of stored A)";
+    case 9: return "invalid argument 9: B is NULL but would be read";
+    case 10: return "invalid argument 10: ldb < max(1, rows of stored B)";
+    case 12: return "invalid argument 12: C is NULL but would be accessed";
+    case 13: return "invalid argument 13: ldc < max(1, m)";
+    case MDG_ERR_HIP: return "HIP runtime error";
+    case MDG_ERR_VARIANT: return "unknown kernel variant";
+    case MDG_ERR_DEVICE: return "current device is not gfx950";
+    case MDG_ERR_SIZE: return "m and n too large for one launch";
+    default: return "unknown status";
+  }
+}
+
+int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                       double beta) {
+  (void)beta;
+  if (!(is_notrans(transa) || is_trans(transa)) || !(is_notrans(transb) || is_trans(transb)))
+    return -1;
+  if (m <= 0 || n <= 0 || k <= 0 || alpha == 0.0) return -1;
+  return pick_variant(m, n, k);
+}
+
+int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double beta, double* C, int64_t ldc, void* stream) {
+  const int info = check_args(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  if (info) return info;
+  if (variant != MDG_VARIANT_AUTO && (variant < 0 || variant >= kNumVariants))
+    return MDG_ERR_VARIANT;
+  if (m == 0 || n == 0) return MDG_SUCCESS;
+  const bool no_product = (alpha == 0.0 || k == 0);
+  if (no_product && beta == 1.0) return MDG_SUCCESS;
+
+  const int dc = device_check();
+  if (dc) return dc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  if (no_product) {
+    const int64_t total = m * n;
+    const int64_t blocks = ceil_div(total, 256) < 65536 ? ceil_div(total, 256) : 65536;
+    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, beta, C,
+                       ldc);
+    return hipGetLastError() == hipSuccess ? MDG_SUCCESS : MDG_ERR_HIP;
+  }
+
+  const int vid = (variant == MDG_VARIANT_AUTO) ? pick_variant(m, n, k) : variant;
+  const Variant& v = kVariants[vid];
+  const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
+  const int64_t tiles = tiles_m * tiles_n;
+  if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;  // beyond one launch's grid
+  GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C};
+  KernelFn fn = v.fn[is_trans(transa) ? 1 : 0][is_trans(transb) ? 1 : 0];
+  hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(v.threads), 0, s, g, (int)tiles_m,
+                     (int)tiles_n);
+  return hipGetLastError() == hipSuccess ? MDG_SUCCESS : MDG_ERR_HIP;
+}
+
+int mdg_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, void* stream) {
+  return mdg_dgemm_ex(MDG_VARIANT_AUTO, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                      ldc, stream);
+}
+
+}  // extern "C"

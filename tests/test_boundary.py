@@ -1,0 +1,107 @@
+"""The C-ABI boundary on the CPU: symbols, argument checks, quick returns, host helpers.
+
+No call here reaches a kernel: every call either fails an argument check or is a
+quick return, both of which return before any HIP call.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1609_00076_amd as mdg
+from paper_1609_00076_amd.build import INCLUDE, LIB_PATH
+
+HEADER = os.path.join(INCLUDE, "mdg.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdg_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB_PATH)
+    names = _declared_functions()
+    assert "mdg_dgemm" in names and len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in mdg.h but not exported"
+        assert hasattr(mdg, name), f"{name} has no Python binding of the same name"
+
+
+def test_version_and_variants():
+    assert mdg.mdg_version() >= 100
+    nv = mdg.mdg_num_variants()
+    assert nv >= 2
+    names = [mdg.mdg_variant_name(v) for v in range(nv)]
+    assert all(names) and len(set(names)) == nv
+    assert mdg.mdg_variant_name(nv) is None and mdg.mdg_variant_name(-1) is None
+    for v in range(nv):
+        mt, nt, kt, threads = mdg.mdg_variant_info(v)
+        assert mt % 16 == 0 and nt % 16 == 0 and kt % 4 == 0 and threads % 64 == 0
+    with pytest.raises(mdg.MdgError):
+        mdg.mdg_variant_info(nv)
+
+
+def _call(ta="N", tb="N", m=4, n=4, k=4, alpha=1.0, A=0x1000, lda=4, B=0x1000, ldb=4,
+          beta=0.0, C=0x1000, ldc=4, variant=None):
+    # Fake non-NULL addresses: every case below fails an argument check or returns early,
+    # so none of them is ever dereferenced.
+    args = (ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc)
+    if variant is None:
+        return mdg.mdg_dgemm(*args)
+    return mdg.mdg_dgemm_ex(variant, *args)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(ta="X"), 1), (dict(ta=""), 1), (dict(tb="q"), 2),
+    (dict(m=-1), 3), (dict(n=-2), 4), (dict(k=-3), 5),
+    (dict(A=None), 7), (dict(lda=3), 8), (dict(ta="T", m=4, k=8, lda=4), 8),
+    (dict(B=None), 9), (dict(ldb=3), 10), (dict(tb="t", n=8, ldb=4), 10),
+    (dict(C=None), 12), (dict(ldc=3), 13),
+    (dict(ta="X", m=-1, lda=0), 1), (dict(m=-1, lda=0), 3),  # first bad argument wins
+    (dict(m=0, lda=0), 8), (dict(n=0, ldc=0), 13),  # ld >= 1 even for empty matrices
+])
+def test_argument_codes(kw, code):
+    assert _call(**kw) == code
+    assert mdg.mdg_status_string(code).startswith(f"invalid argument {code}")
+
+
+def test_null_allowed_where_not_dereferenced_and_quick_returns():
+    # m == 0 or n == 0: nothing touched, NULL everywhere is fine
+    assert _call(m=0, A=None, B=None, C=None, lda=1, ldc=1) == 0
+    assert _call(n=0, A=None, B=None, C=None) == 0
+    # alpha == 0 (or k == 0) with beta == 1: quick return, nothing read
+    assert _call(alpha=0.0, beta=1.0, A=None, B=None, C=None) == 0
+    assert _call(k=0, beta=1.0, A=None, B=None, C=None, lda=4, ldb=1) == 0
+    # alpha == 0 with beta != 1 still needs C (A, B may stay NULL)
+    assert _call(alpha=0.0, beta=2.0, A=None, B=None, C=None) == 12
+
+
+def test_variant_errors():
+    assert _call(variant=mdg.mdg_num_variants(), m=0) == -2
+    assert _call(variant=-7, m=0) == -2
+    assert _call(variant=0, m=-1) == 3  # argument checks come first
+    assert mdg.mdg_status_string(-2) == "unknown kernel variant"
+    assert mdg.mdg_status_string(12345) == "unknown status"
+
+
+def test_select_variant_is_pure_host_logic():
+    nv = mdg.mdg_num_variants()
+    assert mdg.mdg_select_variant("N", "N", 0, 4, 4, 1.0, 0.0) == -1
+    assert mdg.mdg_select_variant("N", "N", 4, 4, 4, 0.0, 0.5) == -1
+    assert mdg.mdg_select_variant("N", "X", 4, 4, 4, 1.0, 0.0) == -1
+    for shape in [(256, 256, 256), (8192, 8192, 8192), (4099, 4099, 4099), (8192, 8192, 64)]:
+        for ta in "NT":
+            for tb in "NT":
+                v = mdg.mdg_select_variant(ta, tb, *shape, 1.0, 1.0)
+                assert 0 <= v < nv
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_1609_00076_amd.binding as b
+    monkeypatch.setattr(b, "_lib", None)
+    monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        b.mdg_version()

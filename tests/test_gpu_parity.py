@@ -1,0 +1,152 @@
+"""GPU parity of mdg_dgemm against the CPU oracle at sizes the oracle finishes quickly.
+
+Integer-valued inputs (entries in {-8..8}, alpha and beta multiples of 1/2): every
+summation order is exact, so the HIP result must equal the oracle bit for bit.
+Uniform[-1,1] inputs: max |C - Cref| / D <= 1e-13 with
+D = |alpha| (|op(A)||op(B)|)_ij + |beta||C0_ij|.
+Shapes span several macro-tiles of every variant and end in ragged tails in m,
+n and k; leading dimensions are rows + 3 (odd, so columns are only 8-byte
+aligned) and the padding holds NaN (A, B) or a signalling-NaN pattern (C).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import check_parity, logical, rel_err, run_mdg, run_oracle, same_bits
+
+pytestmark = pytest.mark.gpu
+
+TRANS = [a + b for a, b in itertools.product("NT", "NT")]
+
+
+def _variants():
+    import paper_1609_00076_amd as mdg
+    return [-1] + list(range(mdg.mdg_num_variants()))
+
+
+VARIANTS = [-1, 0, 1]
+
+SHAPES = [(1, 1, 1), (1, 17, 3), (17, 1, 5), (5, 7, 1), (16, 16, 4), (64, 64, 16), (65, 63, 17),
+          (128, 128, 16), (129, 130, 31), (200, 300, 77), (255, 257, 129), (300, 200, 513)]
+
+
+def _pad3(rows):
+    return max(1, rows) + 3
+
+
+def test_variant_list_is_covered():
+    assert sorted(_variants()) == sorted(VARIANTS), "update VARIANTS for new kernel variants"
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("trans", TRANS)
+def test_workload_256_float(trans, variant):
+    """m = n = k = 256, ld = 260, alpha = 1.5, beta = 0.5, Uniform[-1,1] entries."""
+    p = synth.problem(1, 0, trans[0], trans[1], 256, 256, 256, ld_rule=lambda r: 260)
+    check_parity(p, 1.5, 0.5, variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("trans", TRANS)
+def test_workload_256_integer_bit_exact(trans, variant):
+    p = synth.problem(1, 1, trans[0], trans[1], 256, 256, 256, ld_rule=lambda r: 260, dist="int")
+    check_parity(p, 1.5, 0.5, variant, exact=True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("trans", TRANS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_ragged_integer_bit_exact(shape, trans, variant):
+    m, n, k = shape
+    p = synth.problem(10, 0, trans[0], trans[1], m, n, k, ld_rule=_pad3, dist="int")
+    check_parity(p, 1.5, -0.5, variant, exact=True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("trans", TRANS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_ragged_float(shape, trans, variant):
+    m, n, k = shape
+    p = synth.problem(11, 0, trans[0], trans[1], m, n, k, ld_rule=_pad3)
+    check_parity(p, -0.75, 1.25, variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_beta_zero_never_reads_c(variant):
+    p = synth.problem(12, 0, "N", "T", 150, 97, 40, ld_rule=_pad3)
+    C = p["C"].copy()
+    logical(C, 150, 97, p["ldc"])[:, :] = np.nan
+    got = check_parity(p, 2.0, 0.0, variant, C=C)
+    assert np.all(np.isfinite(logical(got, 150, 97, p["ldc"])))
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0, -2.5])
+def test_alpha_zero_and_k_zero(beta):
+    import paper_1609_00076_amd as mdg
+    import torch
+    m, n = 77, 45
+    p = synth.problem(13, 0, "N", "N", m, n, 9, ld_rule=_pad3)
+    for alpha, k in ((0.0, 9), (1.0, 0)):
+        C0 = p["C"].copy()
+        dC = torch.from_numpy(C0).cuda()
+        # A and B are never read on this path: pass NULL
+        st = mdg.mdg_dgemm("N", "N", m, n, k, alpha, None, p["lda"], None, p["ldb"], beta, dC,
+                           p["ldc"])
+        assert st == 0
+        got = dC.cpu().numpy()
+        want = beta * logical(p["C"], m, n, p["ldc"]) if beta != 0 else np.zeros((m, n))
+        assert np.array_equal(logical(got, m, n, p["ldc"]), want)
+        assert np.array_equal(got.view(np.uint64).reshape(n, -1)[:, m:],
+                              p["C"].view(np.uint64).reshape(n, -1)[:, m:])
+
+
+def test_nan_in_a_poisons_one_row():
+    for trans in TRANS:
+        m, n, k = 140, 70, 50
+        p = synth.problem(14, 0, trans[0], trans[1], m, n, k, ld_rule=_pad3)
+        r, c = synth.stored_dims(trans[0], m, k)
+        st = logical(p["A"], r, c, p["lda"])
+        i0, q0 = 131, 17
+        if trans[0] == "T":
+            st[q0, i0] = np.nan
+        else:
+            st[i0, q0] = np.nan
+        got = logical(run_mdg(p, 1.0, 1.0), m, n, p["ldc"])
+        want = np.zeros((m, n), dtype=bool)
+        want[i0, :] = True
+        assert np.array_equal(np.isnan(got), want), trans
+
+
+def test_all_variants_agree_bitwise_on_integer_data():
+    p = synth.problem(15, 0, "T", "N", 333, 277, 191, ld_rule=_pad3, dist="int")
+    outs = [run_mdg(p, 0.5, 1.5, v) for v in VARIANTS]
+    for o in outs[1:]:
+        assert same_bits(o, outs[0])
+
+
+def test_binding_rejects_short_storage():
+    import paper_1609_00076_amd as mdg
+    import torch
+    a = torch.zeros(10, dtype=torch.float64, device="cuda")
+    c = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        mdg.mdg_dgemm("N", "N", 4, 4, 4, 1.0, a, 4, a, 4, 0.0, c, 4)
+    with pytest.raises(TypeError):
+        mdg.mdg_dgemm("N", "N", 2, 2, 2, 1.0, a.float(), 2, a, 2, 0.0, c, 2)
+
+
+def test_runs_on_a_side_stream():
+    import paper_1609_00076_amd as mdg
+    import torch
+    p = synth.problem(16, 0, "N", "N", 257, 129, 65, ld_rule=_pad3, dist="int")
+    dA, dB, dC = (torch.from_numpy(p[x]).cuda() for x in "ABC")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert mdg.mdg_dgemm("N", "N", 257, 129, 65, 1.0, dA, p["lda"], dB, p["ldb"], 1.0, dC,
+                             p["ldc"], stream=s) == 0
+    s.synchronize()
+    ref, _ = run_oracle(p, 1.0, 1.0)
+    assert same_bits(logical(dC.cpu().numpy(), 257, 129, p["ldc"]), logical(ref, 257, 129, p["ldc"]))

@@ -43,7 +43,8 @@
  * is untouched. No entry point prints or aborts.
  *
  * Thread safety: every entry point is reentrant; the only global state is a
- * read-only table of kernel variants built at load time.
+ * read-only table of kernel variants and a per-device memo of the architecture
+ * check.
  */
 #ifndef MDG_H
 #define MDG_H
@@ -103,6 +104,12 @@ int mdg_variant_info(int variant, int *mt, int *nt, int *kt, int *threads);
 
 /* Static description of a status code (never NULL). */
 const char *mdg_status_string(int status);
+
+/*
+ * The raw hipError_t of the last HIP call that failed inside this library on the
+ * calling thread (0 if none): the detail behind an MDG_ERR_HIP return.
+ */
+int mdg_last_hip_error(void);
 
 /* Library version, major*10000 + minor*100 + patch. */
 int mdg_version(void);

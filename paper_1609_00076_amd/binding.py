@@ -22,18 +22,38 @@ _lib = None
 class MdgError(RuntimeError):
     def __init__(self, status: int):
         self.status = status
-        super().__init__(f"mdg status {status}: {mdg_status_string(status)}")
+        detail = f" (hipError_t {mdg_last_hip_error()})" if status == -1 else ""
+        super().__init__(f"mdg status {status}: {mdg_status_string(status)}{detail}")
+
+
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
 
 
 def load():
-    """Open libmdg.so (built in-tree by paper_1609_00076_amd.build); raise if absent."""
+    """Open libmdg.so (built in-tree by paper_1609_00076_amd.build); raise if absent.
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already uses: torch wheels carry their own libamdhip64, and a second runtime
+    in the same process cannot see torch's device memory or streams.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1609_00076_amd.build` "
                           "(or __graft_entry__.build()) first")
+    import torch  # noqa: F401  (loads torch's HIP runtime before ours is resolved)
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise ImportError("two HIP runtimes are mapped into this process (" + ", ".join(runtimes) +
+                          "); libmdg.so must share torch's runtime")
     i64, dbl, vp, ch, ci = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char, ctypes.c_int
     gemm_args = [ch, ch, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp]
     lib.mdg_dgemm.argtypes = gemm_args
@@ -52,6 +72,8 @@ def load():
     lib.mdg_status_string.restype = ctypes.c_char_p
     lib.mdg_version.argtypes = []
     lib.mdg_version.restype = ci
+    lib.mdg_last_hip_error.argtypes = []
+    lib.mdg_last_hip_error.restype = ci
     _lib = lib
     return lib
 
@@ -161,6 +183,10 @@ def mdg_status_string(status: int) -> str:
 
 def mdg_version() -> int:
     return load().mdg_version()
+
+
+def mdg_last_hip_error() -> int:
+    return load().mdg_last_hip_error()
 
 
 def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None, variant=-1):

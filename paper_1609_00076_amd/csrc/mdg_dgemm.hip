@@ -15,12 +15,15 @@
 // outside C are masked, so the padding rows of every operand are never read or written.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 
 #include "mdg.h"
 
-namespace {
+// Kernels need external linkage so the runtime can resolve them by name at launch; everything
+// in this namespace is private to the library all the same (only the extern "C" API is exported).
+namespace mdg_impl {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -310,20 +313,51 @@ int pick_variant(int64_t m, int64_t n, int64_t /*k*/) {
   return big_tiles >= 512 ? 0 : 1;
 }
 
-int device_check() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MDG_ERR_HIP;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MDG_ERR_HIP;
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MDG_ERR_DEVICE;
-  return 0;
+thread_local int t_last_hip_error = 0;  // raw hipError_t of the last failed HIP call, per thread
+
+int hip_fail(hipError_t e) {
+  t_last_hip_error = (int)e;
+  return MDG_ERR_HIP;
 }
 
-}  // namespace
+// Per-device memo of the architecture check (0 unknown, 1 gfx950, 2 other). Concurrent first
+// calls may both query; they store the same value.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_arch_ok[kMaxDevices];
+
+int device_check() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  int known = (dev >= 0 && dev < kMaxDevices) ? g_arch_ok[dev].load(std::memory_order_relaxed) : 0;
+  if (known == 0) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    known = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    if (dev >= 0 && dev < kMaxDevices) g_arch_ok[dev].store(known, std::memory_order_relaxed);
+  }
+  return known == 1 ? 0 : MDG_ERR_DEVICE;
+}
+
+// Launch and report this launch's own status (hipLaunchKernel's return value, not the
+// thread's sticky last-error, which may hold an unrelated earlier failure).
+template <typename... Args>
+int launch(const void* fn, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  void* argv[] = {static_cast<void*>(&args)...};
+  hipError_t e = hipLaunchKernel(fn, grid, block, argv, 0, s);
+  return e == hipSuccess ? MDG_SUCCESS : hip_fail(e);
+}
+
+}  // namespace mdg_impl
+
+using namespace mdg_impl;
 
 extern "C" {
 
 int mdg_version(void) { return kVersion; }
+
+int mdg_last_hip_error(void) { return t_last_hip_error; }
 
 int mdg_num_variants(void) { return kNumVariants; }
 
@@ -390,9 +424,8 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   if (no_product) {
     const int64_t total = m * n;
     const int64_t blocks = ceil_div(total, 256) < 65536 ? ceil_div(total, 256) : 65536;
-    hipLaunchKernelGGL(scale_c_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, n, beta, C,
-                       ldc);
-    return hipGetLastError() == hipSuccess ? MDG_SUCCESS : MDG_ERR_HIP;
+    return launch(reinterpret_cast<const void*>(&scale_c_kernel), dim3((unsigned)blocks), dim3(256),
+                  s, m, n, beta, C, ldc);
   }
 
   const int vid = (variant == MDG_VARIANT_AUTO) ? pick_variant(m, n, k) : variant;
@@ -402,9 +435,8 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;  // beyond one launch's grid
   GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C};
   KernelFn fn = v.fn[is_trans(transa) ? 1 : 0][is_trans(transb) ? 1 : 0];
-  hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(v.threads), 0, s, g, (int)tiles_m,
-                     (int)tiles_n);
-  return hipGetLastError() == hipSuccess ? MDG_SUCCESS : MDG_ERR_HIP;
+  return launch(reinterpret_cast<const void*>(fn), dim3((unsigned)tiles), dim3(v.threads), s, g,
+                (int)tiles_m, (int)tiles_n);
 }
 
 int mdg_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,

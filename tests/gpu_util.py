@@ -31,7 +31,8 @@ def run_mdg(p, alpha, beta, variant=-1, C=None):
     dC = to_dev(p["C"] if C is None else C)
     st = mdg.mdg_dgemm_ex(variant, p["transa"], p["transb"], p["m"], p["n"], p["k"], alpha,
                           dA, p["lda"], dB, p["ldb"], beta, dC, p["ldc"])
-    assert st == 0, f"mdg_dgemm_ex returned {st}: {mdg.mdg_status_string(st)}"
+    assert st == 0, (f"mdg_dgemm_ex returned {st}: {mdg.mdg_status_string(st)} "
+                     f"(hipError_t {mdg.mdg_last_hip_error()})")
     torch.cuda.synchronize()
     return dC.cpu().numpy()
 

@@ -36,14 +36,16 @@ struct GemmArgs {
   const double* A;
   const double* B;
   double* C;
+  int64_t ext_a, ext_b;  // storage extent of A and B in elements: (cols-1)*ld + rows
 };
 
 // ------------------------------------------------------------------------------------------------
 // Tile configuration. MT x NT macro-tile per workgroup, KT-deep k-panels, WM x WN per wave.
 // ------------------------------------------------------------------------------------------------
-template <int MT_, int NT_, int KT_, int WM_, int WN_>
+template <int MT_, int NT_, int KT_, int WM_, int WN_, int MIN_WAVES_PER_EU_>
 struct Cfg {
   static constexpr int MT = MT_, NT = NT_, KT = KT_, WM = WM_, WN = WN_;
+  static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;  // occupancy target per SIMD
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
   static constexpr int WAVES = WAVES_M * WAVES_N;
   static constexpr int THREADS = WAVES * 64;
@@ -75,66 +77,79 @@ __device__ __forceinline__ void tile_coords(int wg, int nwg, int tiles_m, int ti
   tn = r / gsize;
 }
 
-// Load this thread's share of the op(A) panel (rows row0.., k-indices k0..) into registers.
-// TA == false: A is stored m x k (contiguous along m); consecutive threads take consecutive rows.
-// TA == true : A is stored k x m (contiguous along k); consecutive threads take consecutive k.
-template <class C, bool TA>
-__device__ __forceinline__ void load_a(const GemmArgs& g, int64_t row0, int64_t k0, int tid,
-                                       double (&ra)[C::A_PER_THREAD]) {
+// ------------------------------------------------------------------------------------------------
+// Global -> register panel loads through buffer resources.
+//
+// Each k-panel of op(A) (MT x KT) and op(B) (KT x NT) is read through a buffer resource whose base
+// is the panel's first element and whose size is the rest of the matrix's storage (its exact
+// extent, (cols-1)*ld + rows elements, minus the panel origin). A read beyond the matrix's last
+// element returns 0 instead of faulting, so no load needs an address clamp. Rows of op(A) beyond m
+// and columns of op(B) beyond n may read other data of the same storage; they only feed rows and
+// columns of the tile that are never stored. Entries with k-index >= k must be zero in both
+// operands (0 * NaN would poison real results); those beyond the last column of the storage are
+// zero by the bound above, and the rest are zeroed explicitly in the last, ragged k-panel.
+// ------------------------------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ rsrc_t make_rsrc(const double* base, int64_t rem_elems) {
+  // num_records is in bytes and 32 bits wide; beyond 4 GiB the bound cannot bind inside a panel.
+  const uint32_t num = rem_elems <= 0 ? 0u
+                       : rem_elems >= (int64_t)0x1FFFFFFF ? 0xFFFFFFFFu
+                                                          : (uint32_t)(rem_elems * 8);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)num,
+                                           kBufferWord3);
+}
+
+__device__ __forceinline__ double load_f64(rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+
+// Per-thread placement of one operand's panel: element r of this thread sits at row `row[r]`,
+// k-index `kq[r]` of the panel, `off[r]` bytes from the panel origin in global memory, and at
+// `lds[r]` in the k-major LDS panel (index q*LDS + row).
+template <int PER_THREAD>
+struct PanelMap {
+  uint32_t off[PER_THREAD];
+  int lds[PER_THREAD];
+  int kq[PER_THREAD];
+};
+
+// CONTIG_K: the stored operand is contiguous along k (op(A) with transa = T, op(B) with
+// transb = N); otherwise it is contiguous along the panel's rows (m for A, n for B).
+template <int ROWS, int KT, int THREADS, int LDS, bool CONTIG_K, int PER_THREAD>
+__device__ __forceinline__ void make_map(PanelMap<PER_THREAD>& mp, int tid, int64_t ld) {
 #pragma unroll
-  for (int r = 0; r < C::A_PER_THREAD; ++r) {
-    int e = tid + r * C::THREADS;
+  for (int r = 0; r < PER_THREAD; ++r) {
+    const int e = tid + r * THREADS;
     int i, q;
-    if (TA) { q = e % C::KT; i = e / C::KT; }
-    else    { i = e % C::MT; q = e / C::MT; }
-    int64_t gi = row0 + i, gq = k0 + q;
-    bool ok = gi < g.m && gq < g.k;
-    int64_t ci = ok ? gi : g.m - 1, cq = ok ? gq : g.k - 1;
-    double v = TA ? g.A[ci * g.lda + cq] : g.A[cq * g.lda + ci];
-    ra[r] = ok ? v : 0.0;
+    if (CONTIG_K) { q = e % KT; i = e / KT; }
+    else          { i = e % ROWS; q = e / ROWS; }
+    mp.off[r] = (uint32_t)((CONTIG_K ? (q + (int64_t)i * ld) : (i + (int64_t)q * ld)) * 8);
+    mp.lds[r] = q * LDS + i;
+    mp.kq[r] = q;
   }
 }
 
-template <class C, bool TA>
-__device__ __forceinline__ void store_a(double* As, int tid, const double (&ra)[C::A_PER_THREAD]) {
+template <int PER_THREAD>
+__device__ __forceinline__ void load_panel(const PanelMap<PER_THREAD>& mp, rsrc_t r,
+                                           double (&v)[PER_THREAD]) {
 #pragma unroll
-  for (int r = 0; r < C::A_PER_THREAD; ++r) {
-    int e = tid + r * C::THREADS;
-    int i, q;
-    if (TA) { q = e % C::KT; i = e / C::KT; }
-    else    { i = e % C::MT; q = e / C::MT; }
-    As[q * C::LDS_A + i] = ra[r];
-  }
+  for (int e = 0; e < PER_THREAD; ++e) v[e] = load_f64(r, mp.off[e]);
 }
 
-// op(B) panel: TB == false: B stored k x n (contiguous along k); TB == true: n x k (along n).
-template <class C, bool TB>
-__device__ __forceinline__ void load_b(const GemmArgs& g, int64_t col0, int64_t k0, int tid,
-                                       double (&rb)[C::B_PER_THREAD]) {
+template <int PER_THREAD>
+__device__ __forceinline__ void mask_k_tail(const PanelMap<PER_THREAD>& mp, int k_left,
+                                            double (&v)[PER_THREAD]) {
 #pragma unroll
-  for (int r = 0; r < C::B_PER_THREAD; ++r) {
-    int e = tid + r * C::THREADS;
-    int j, q;
-    if (TB) { j = e % C::NT; q = e / C::NT; }
-    else    { q = e % C::KT; j = e / C::KT; }
-    int64_t gj = col0 + j, gq = k0 + q;
-    bool ok = gj < g.n && gq < g.k;
-    int64_t cj = ok ? gj : g.n - 1, cq = ok ? gq : g.k - 1;
-    double v = TB ? g.B[cq * g.ldb + cj] : g.B[cj * g.ldb + cq];
-    rb[r] = ok ? v : 0.0;
-  }
+  for (int e = 0; e < PER_THREAD; ++e) v[e] = mp.kq[e] < k_left ? v[e] : 0.0;
 }
 
-template <class C, bool TB>
-__device__ __forceinline__ void store_b(double* Bs, int tid, const double (&rb)[C::B_PER_THREAD]) {
+template <int PER_THREAD>
+__device__ __forceinline__ void store_panel(const PanelMap<PER_THREAD>& mp, double* lds,
+                                            const double (&v)[PER_THREAD]) {
 #pragma unroll
-  for (int r = 0; r < C::B_PER_THREAD; ++r) {
-    int e = tid + r * C::THREADS;
-    int j, q;
-    if (TB) { j = e % C::NT; q = e / C::NT; }
-    else    { q = e % C::KT; j = e / C::KT; }
-    Bs[q * C::LDS_B + j] = rb[r];
-  }
+  for (int e = 0; e < PER_THREAD; ++e) lds[mp.lds[e]] = v[e];
 }
 
 // One workgroup computes one MT x NT tile of C.
@@ -146,7 +161,7 @@ __device__ __forceinline__ void store_b(double* Bs, int tid, const double (&rb)[
 // rows of one column of C, which makes the epilogue's loads and stores of column-major C
 // contiguous 128-byte runs.
 template <class C, bool TA, bool TB>
-__global__ void __launch_bounds__(C::THREADS)
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::MIN_WAVES_PER_EU)))
 dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ double As[2][C::KT * C::LDS_A];
   __shared__ double Bs[2][C::KT * C::LDS_B];
@@ -162,6 +177,17 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   const int64_t row0 = (int64_t)tm * C::MT;
   const int64_t col0 = (int64_t)tn * C::NT;
 
+  PanelMap<C::A_PER_THREAD> ma;
+  PanelMap<C::B_PER_THREAD> mb;
+  make_map<C::MT, C::KT, C::THREADS, C::LDS_A, TA>(ma, tid, g.lda);
+  make_map<C::NT, C::KT, C::THREADS, C::LDS_B, !TB>(mb, tid, g.ldb);
+
+  // Panel origins (elements from the matrix base) and their step per k-panel.
+  const int64_t a_org = TA ? row0 * g.lda : row0;
+  const int64_t a_step = TA ? (int64_t)C::KT : (int64_t)C::KT * g.lda;
+  const int64_t b_org = TB ? col0 : col0 * g.ldb;
+  const int64_t b_step = TB ? (int64_t)C::KT * g.ldb : (int64_t)C::KT;
+
   d4 acc[C::BM][C::BN];
 #pragma unroll
   for (int bi = 0; bi < C::BM; ++bi)
@@ -169,35 +195,41 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
     for (int bj = 0; bj < C::BN; ++bj) acc[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
 
   double ra[C::A_PER_THREAD], rb[C::B_PER_THREAD];
-  const int64_t num_k = (g.k + C::KT - 1) / C::KT;
+  const int num_k = (int)((g.k + C::KT - 1) / C::KT);
+  const int k_left_last = (int)(g.k - (int64_t)(num_k - 1) * C::KT);  // 1..KT
 
-  load_a<C, TA>(g, row0, 0, tid, ra);
-  load_b<C, TB>(g, col0, 0, tid, rb);
-  store_a<C, TA>(As[0], tid, ra);
-  store_b<C, TB>(Bs[0], tid, rb);
+  auto fetch = [&](int kt) {
+    const int64_t ao = a_org + kt * a_step, bo = b_org + kt * b_step;
+    load_panel(ma, make_rsrc(g.A + ao, g.ext_a - ao), ra);
+    load_panel(mb, make_rsrc(g.B + bo, g.ext_b - bo), rb);
+    if (kt == num_k - 1 && k_left_last < C::KT) {  // uniform branch: ragged last panel only
+      mask_k_tail(ma, k_left_last, ra);
+      mask_k_tail(mb, k_left_last, rb);
+    }
+  };
+
+  fetch(0);
+  store_panel(ma, As[0], ra);
+  store_panel(mb, Bs[0], rb);
   __syncthreads();
 
   const int l16 = lane & 15, lq = lane >> 4;
-  const int a_off = wave_m * C::WM + l16;  // row within the panel this lane feeds
-  const int b_off = wave_n * C::WN + l16;  // column within the panel this lane feeds
+  const int a_frag = lq * C::LDS_A + wave_m * C::WM + l16;  // this lane's A fragment at k-step 0
+  const int b_frag = lq * C::LDS_B + wave_n * C::WN + l16;
 
-  for (int64_t kt = 0; kt < num_k; ++kt) {
+  for (int kt = 0; kt < num_k; ++kt) {
     const int buf = kt & 1;
     const bool more = kt + 1 < num_k;
-    if (more) {
-      load_a<C, TA>(g, row0, (kt + 1) * C::KT, tid, ra);
-      load_b<C, TB>(g, col0, (kt + 1) * C::KT, tid, rb);
-    }
-    const double* as = As[buf];
-    const double* bs = Bs[buf];
+    if (more) fetch(kt + 1);
+    const double* as = As[buf] + a_frag;
+    const double* bs = Bs[buf] + b_frag;
 #pragma unroll
     for (int s = 0; s < C::KT / 4; ++s) {
-      const int q = 4 * s + lq;
       double af[C::BM], bf[C::BN];
 #pragma unroll
-      for (int bi = 0; bi < C::BM; ++bi) af[bi] = as[q * C::LDS_A + a_off + 16 * bi];
+      for (int bi = 0; bi < C::BM; ++bi) af[bi] = as[4 * s * C::LDS_A + 16 * bi];
 #pragma unroll
-      for (int bj = 0; bj < C::BN; ++bj) bf[bj] = bs[q * C::LDS_B + b_off + 16 * bj];
+      for (int bj = 0; bj < C::BN; ++bj) bf[bj] = bs[4 * s * C::LDS_B + 16 * bj];
 #pragma unroll
       for (int bi = 0; bi < C::BM; ++bi)
 #pragma unroll
@@ -205,25 +237,28 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
           acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
     }
     if (more) {
-      store_a<C, TA>(As[buf ^ 1], tid, ra);
-      store_b<C, TB>(Bs[buf ^ 1], tid, rb);
+      store_panel(ma, As[buf ^ 1], ra);
+      store_panel(mb, Bs[buf ^ 1], rb);
     }
     __syncthreads();
   }
 
   // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
   const double alpha = g.alpha, beta = g.beta;
+  const int64_t i0 = row0 + wave_m * C::WM + l16;
+  const int64_t j0 = col0 + wave_n * C::WN + lq;
+  double* cbase = g.C + j0 * g.ldc + i0;
 #pragma unroll
-  for (int bi = 0; bi < C::BM; ++bi) {
-    const int64_t i = row0 + wave_m * C::WM + 16 * bi + l16;
-    if (i >= g.m) continue;
+  for (int bj = 0; bj < C::BN; ++bj) {
 #pragma unroll
-    for (int bj = 0; bj < C::BN; ++bj) {
+    for (int r = 0; r < 4; ++r) {
+      const int64_t dj = 16 * bj + 4 * r;
+      if (j0 + dj >= g.n) continue;
+      double* ccol = cbase + dj * g.ldc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t j = col0 + wave_n * C::WN + 16 * bj + lq + 4 * r;
-        if (j < g.n) {
-          double* c = g.C + j * g.ldc + i;
+      for (int bi = 0; bi < C::BM; ++bi) {
+        if (i0 + 16 * bi < g.m) {
+          double* c = ccol + 16 * bi;
           double v = alpha * acc[bi][bj][r];
           if (beta != 0.0) v += beta * *c;
           *c = v;
@@ -249,8 +284,8 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
 // ------------------------------------------------------------------------------------------------
 // Variant table.
 // ------------------------------------------------------------------------------------------------
-using Big = Cfg<128, 128, 16, 64, 64>;    // 4 waves, each 64x64 (16 MFMA chains)
-using Small = Cfg<64, 64, 16, 32, 32>;    // 4 waves, each 32x32 (4 MFMA chains)
+using Big = Cfg<128, 128, 16, 64, 64, 2>;  // 4 waves, each 64x64 (16 MFMA chains)
+using Small = Cfg<64, 64, 16, 32, 32, 4>;  // 4 waves, each 32x32 (4 MFMA chains)
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -433,7 +468,10 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;  // beyond one launch's grid
-  GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C};
+  const int64_t rows_a = is_trans(transa) ? k : m, cols_a = is_trans(transa) ? m : k;
+  const int64_t rows_b = is_trans(transb) ? n : k, cols_b = is_trans(transb) ? k : n;
+  GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C,
+             (cols_a - 1) * lda + rows_a, (cols_b - 1) * ldb + rows_b};
   KernelFn fn = v.fn[is_trans(transa) ? 1 : 0][is_trans(transb) ? 1 : 0];
   return launch(reinterpret_cast<const void*>(fn), dim3((unsigned)tiles), dim3(v.threads), s, g,
                 (int)tiles_m, (int)tiles_n);

@@ -85,17 +85,18 @@ def hbm_bytes(p, beta=1.0):
     return 8.0 * (m * k + k * n + m * n * (beta != 0.0) + m * n)
 
 
-def kernel_key(mdg, p):
-    v = mdg.mdg_select_variant(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, 1.0)
+def kernel_key(mdg, p, variant=-1):
+    v = variant if variant >= 0 else \
+        mdg.mdg_select_variant(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, 1.0)
     return f"{mdg.mdg_variant_name(v)}[{p['transa']}{p['transb']}]"
 
 
-def run_step(mdg, probs, events=None):
+def run_step(mdg, probs, events=None, variant=-1):
     for i, p in enumerate(probs):
         if events is not None:
             events[i][0].record()
-        st = mdg.mdg_dgemm(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, p["A"],
-                           p["lda"], p["B"], p["ldb"], 1.0, p["C"], p["ldc"])
+        st = mdg.mdg_dgemm_ex(variant, p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0,
+                              p["A"], p["lda"], p["B"], p["ldb"], 1.0, p["C"], p["ldc"])
         if st:
             raise RuntimeError(f"mdg_dgemm failed: {mdg.mdg_status_string(st)}")
         if events is not None:
@@ -153,6 +154,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of CPU time for the oracle baseline (0 disables it)")
     ap.add_argument("--shapes", default="", help="comma list of sizes and/or 'skinny' (default: all)")
+    ap.add_argument("--trans", default="", help="comma list of NN,NT,TN,TT (default: all four)")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="force one kernel variant for every GEMM (default -1: the library's choice)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes three times (the "
+                         "reference kernel for scaling HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -168,14 +175,29 @@ def main():
         print("bench.py: no HIP device visible", file=sys.stderr)
         sys.exit(1)
 
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        src = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
+        return
+
     shapes_filter = None
     if args.shapes:
         shapes_filter = {int(s) if s.isdigit() else s for s in args.shapes.split(",")}
     probs = build_problems(torch, shapes_filter)
+    if args.trans:
+        keep = set(args.trans.upper().split(","))
+        probs = [p for p in probs if p["transa"] + p["transb"] in keep]
+    subset = bool(shapes_filter or args.trans)
     torch.cuda.synchronize()
 
     for w in range(args.warmup):
-        run_step(mdg, probs)
+        run_step(mdg, probs, variant=args.variant)
         torch.cuda.synchronize()
         log(f"[bench] warmup step {w + 1}/{args.warmup} done")
 
@@ -185,7 +207,7 @@ def main():
     torch.cuda.synchronize()
     start.record()
     for s in range(args.steps):
-        run_step(mdg, probs, ev[s])
+        run_step(mdg, probs, ev[s], variant=args.variant)
     stop.record()
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
@@ -200,7 +222,7 @@ def main():
     for s in range(args.steps):
         for i, p in enumerate(probs):
             ms = ev[s][i][0].elapsed_time(ev[s][i][1])
-            key = kernel_key(mdg, p)
+            key = kernel_key(mdg, p, args.variant)
             d = per_kernel.setdefault(key, dict(ms=0.0, flops=0.0, bytes=0.0, launches=0))
             d["ms"] += ms
             d["flops"] += flops(p)
@@ -251,8 +273,10 @@ def main():
         "config": {
             "workload": "native dgemm sweep: (N|T)x(N|T) x square m=n=k in "
                         "{1024,2048,4096,4099,8192,16384} + 8192x8192x64; ld = stored rows rounded "
-                        "up to a multiple of 8; alpha=beta=1" if not shapes_filter else
-                        f"native dgemm subset {sorted(map(str, shapes_filter))}",
+                        "up to a multiple of 8; alpha=beta=1" if not subset else
+                        "native dgemm subset: " + ", ".join(
+                            sorted({f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}"
+                                    for p in probs})),
             "gemms_per_step": len(probs),
             "flops_per_step": step_flops,
         },

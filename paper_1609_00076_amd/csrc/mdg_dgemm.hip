@@ -42,22 +42,38 @@ struct GemmArgs {
 // ------------------------------------------------------------------------------------------------
 // Tile configuration. MT x NT macro-tile per workgroup, KT-deep k-panels, WM x WN per wave.
 // ------------------------------------------------------------------------------------------------
-template <int MT_, int NT_, int KT_, int WM_, int WN_, int MIN_WAVES_PER_EU_>
+template <int MT_, int NT_, int KT_, int WM_, int WN_, int MIN_WAVES_PER_EU_, int PAD_MODE_ = 1,
+          bool PREFETCH_C_ = false>
 struct Cfg {
   static constexpr int MT = MT_, NT = NT_, KT = KT_, WM = WM_, WN = WN_;
   static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;  // occupancy target per SIMD
+  // LDS padding: 0 = two doubles per k-row for both operands; 1 = sixteen doubles (128 bytes)
+  // for an operand whose global rows run along m or n, which makes the fragment reads of
+  // consecutive k-rows fall in disjoint bank halves.
+  static constexpr int PAD_MODE = PAD_MODE_;
+  // Load the old C of this thread's outputs before the k-loop (for short k, where the epilogue's
+  // HBM traffic would otherwise start only after the arithmetic).
+  static constexpr bool PREFETCH_C = PREFETCH_C_;
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
   static constexpr int WAVES = WAVES_M * WAVES_N;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int BM = WM / 16, BN = WN / 16;  // 16x16 MFMA blocks per wave
-  // LDS rows are k-major: panel element (row r, k-index q) sits at q*LDS_A + r. Two extra doubles
-  // per row shift consecutive k-rows across banks.
-  static constexpr int LDS_A = MT + 2, LDS_B = NT + 2;
   static constexpr int A_PER_THREAD = MT * KT / THREADS;
   static constexpr int B_PER_THREAD = KT * NT / THREADS;
   static_assert(MT % WM == 0 && NT % WN == 0, "wave grid");
   static_assert(WM % 16 == 0 && WN % 16 == 0 && KT % 4 == 0, "MFMA shape");
   static_assert((MT * KT) % THREADS == 0 && (KT * NT) % THREADS == 0, "panel split");
+  static_assert(THREADS <= 1024, "workgroup size");
+};
+
+// LDS panels are k-major: element (row r, k-index q) sits at q*STRIDE + r. An operand whose global
+// rows run along k is written down a column (16 lanes, 16 k-rows), so its k-rows are two doubles
+// apart in bank space (16-byte shift per row, conflict-free writes); an operand whose global rows
+// run along m or n is written along a k-row, so its stride can be chosen for the reads instead.
+template <class C, bool TA, bool TB>
+struct LdsLayout {
+  static constexpr int A = (TA || C::PAD_MODE == 0) ? C::MT + 2 : C::MT + 16;
+  static constexpr int B = (!TB || C::PAD_MODE == 0) ? C::NT + 2 : C::NT + 16;
 };
 
 // XCD-aware tile order. Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
@@ -163,24 +179,51 @@ __device__ __forceinline__ void store_panel(const PanelMap<PER_THREAD>& mp, doub
 template <class C, bool TA, bool TB>
 __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::MIN_WAVES_PER_EU)))
 dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
-  __shared__ double As[2][C::KT * C::LDS_A];
-  __shared__ double Bs[2][C::KT * C::LDS_B];
+  using L = LdsLayout<C, TA, TB>;
+  __shared__ double As[2][C::KT * L::A];
+  __shared__ double Bs[2][C::KT * L::B];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wave_m = wave % C::WAVES_M;
   const int wave_n = wave / C::WAVES_M;
+  const int l16 = lane & 15, lq = lane >> 4;
 
   int tm, tn;
   tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
   const int64_t row0 = (int64_t)tm * C::MT;
   const int64_t col0 = (int64_t)tn * C::NT;
 
+  // This lane's outputs: rows i0 + 16*bi, columns j0 + 16*bj + 4*r.
+  const int64_t i0 = row0 + wave_m * C::WM + l16;
+  const int64_t j0 = col0 + wave_n * C::WN + lq;
+  double* const cbase = g.C + j0 * g.ldc + i0;
+  const double alpha = g.alpha, beta = g.beta;
+
+  // Old C of this lane's outputs in column block bj (BM x 4 values), all loads issued together.
+  auto load_c_block = [&](int bj, double (&dst)[C::BM][4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t dj = 16 * bj + 4 * r;
+      const bool col_ok = j0 + dj < g.n;
+#pragma unroll
+      for (int bi = 0; bi < C::BM; ++bi)
+        dst[bi][r] = (col_ok && i0 + 16 * bi < g.m) ? cbase[dj * g.ldc + 16 * bi] : 0.0;
+    }
+  };
+  // With PREFETCH_C the whole tile's old C is loaded before the k-loop, so that its HBM reads
+  // overlap the arithmetic; otherwise the epilogue loads it one column block at a time.
+  double c0[C::PREFETCH_C ? C::BN : 1][C::BM][4];
+  if (C::PREFETCH_C && beta != 0.0) {
+#pragma unroll
+    for (int bj = 0; bj < C::BN; ++bj) load_c_block(bj, c0[C::PREFETCH_C ? bj : 0]);
+  }
+
   PanelMap<C::A_PER_THREAD> ma;
   PanelMap<C::B_PER_THREAD> mb;
-  make_map<C::MT, C::KT, C::THREADS, C::LDS_A, TA>(ma, tid, g.lda);
-  make_map<C::NT, C::KT, C::THREADS, C::LDS_B, !TB>(mb, tid, g.ldb);
+  make_map<C::MT, C::KT, C::THREADS, L::A, TA>(ma, tid, g.lda);
+  make_map<C::NT, C::KT, C::THREADS, L::B, !TB>(mb, tid, g.ldb);
 
   // Panel origins (elements from the matrix base) and their step per k-panel.
   const int64_t a_org = TA ? row0 * g.lda : row0;
@@ -213,9 +256,8 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   store_panel(mb, Bs[0], rb);
   __syncthreads();
 
-  const int l16 = lane & 15, lq = lane >> 4;
-  const int a_frag = lq * C::LDS_A + wave_m * C::WM + l16;  // this lane's A fragment at k-step 0
-  const int b_frag = lq * C::LDS_B + wave_n * C::WN + l16;
+  const int a_frag = lq * L::A + wave_m * C::WM + l16;  // this lane's A fragment at k-step 0
+  const int b_frag = lq * L::B + wave_n * C::WN + l16;
 
   for (int kt = 0; kt < num_k; ++kt) {
     const int buf = kt & 1;
@@ -227,9 +269,9 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
     for (int s = 0; s < C::KT / 4; ++s) {
       double af[C::BM], bf[C::BN];
 #pragma unroll
-      for (int bi = 0; bi < C::BM; ++bi) af[bi] = as[4 * s * C::LDS_A + 16 * bi];
+      for (int bi = 0; bi < C::BM; ++bi) af[bi] = as[4 * s * L::A + 16 * bi];
 #pragma unroll
-      for (int bj = 0; bj < C::BN; ++bj) bf[bj] = bs[4 * s * C::LDS_B + 16 * bj];
+      for (int bj = 0; bj < C::BN; ++bj) bf[bj] = bs[4 * s * L::B + 16 * bj];
 #pragma unroll
       for (int bi = 0; bi < C::BM; ++bi)
 #pragma unroll
@@ -244,24 +286,26 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   }
 
   // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
-  const double alpha = g.alpha, beta = g.beta;
-  const int64_t i0 = row0 + wave_m * C::WM + l16;
-  const int64_t j0 = col0 + wave_n * C::WN + lq;
-  double* cbase = g.C + j0 * g.ldc + i0;
 #pragma unroll
   for (int bj = 0; bj < C::BN; ++bj) {
+    double cb[C::BM][4];
+    if (C::PREFETCH_C) {
+#pragma unroll
+      for (int bi = 0; bi < C::BM; ++bi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cb[bi][r] = c0[C::PREFETCH_C ? bj : 0][bi][r];
+    } else if (beta != 0.0) {
+      load_c_block(bj, cb);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t dj = 16 * bj + 4 * r;
       if (j0 + dj >= g.n) continue;
-      double* ccol = cbase + dj * g.ldc;
 #pragma unroll
       for (int bi = 0; bi < C::BM; ++bi) {
         if (i0 + 16 * bi < g.m) {
-          double* c = ccol + 16 * bi;
-          double v = alpha * acc[bi][bj][r];
-          if (beta != 0.0) v += beta * *c;
-          *c = v;
+          const double v = alpha * acc[bi][bj][r];
+          cbase[dj * g.ldc + 16 * bi] = (beta != 0.0) ? v + beta * cb[bi][r] : v;
         }
       }
     }
@@ -284,31 +328,70 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
 // ------------------------------------------------------------------------------------------------
 // Variant table.
 // ------------------------------------------------------------------------------------------------
-using Big = Cfg<128, 128, 16, 64, 64, 2>;  // 4 waves, each 64x64 (16 MFMA chains)
-using Small = Cfg<64, 64, 16, 32, 32, 4>;  // 4 waves, each 32x32 (4 MFMA chains)
+using Big = Cfg<128, 128, 16, 64, 64, 2, 0>;     // 4 waves, each 64x64 (16 MFMA chains)
+using Small = Cfg<64, 64, 16, 32, 32, 4, 0>;     // 4 waves, each 32x32 (4 MFMA chains)
+using Big8a = Cfg<128, 128, 16, 32, 64, 4, 0>;   // 8 waves, each 32x64
+using Big8b = Cfg<128, 128, 16, 64, 32, 4, 0>;   // 8 waves, each 64x32
+using Tall = Cfg<256, 128, 16, 64, 64, 2, 0>;    // 8 waves, each 64x64
+using Wide = Cfg<128, 256, 16, 64, 64, 2, 0>;    // 8 waves, each 64x64
+using Big16 = Cfg<128, 128, 16, 32, 32, 8, 0>;   // 16 waves, each 32x32
+using Tall16 = Cfg<256, 128, 16, 64, 32, 4, 0>;  // 16 waves, each 64x32
+using Mid8 = Cfg<128, 64, 16, 32, 32, 6, 0>;     // 8 waves, each 32x32
+using Big16p = Cfg<128, 128, 16, 32, 32, 8, 1>;  // Big16 with read-friendly LDS padding
+using Small16 = Cfg<64, 64, 16, 16, 16, 8, 1>;   // 16 waves, each 16x16 (one MFMA chain)
+using Skinny = Cfg<64, 64, 16, 32, 32, 4, 1, true>;  // 4 waves of 32x32, old C loaded up front
 
 typedef void (*KernelFn)(GemmArgs, int, int);
+
+constexpr int kCUs = 256;             // MI355X compute units
+constexpr int kLdsPerCU = 160 * 1024;  // bytes of LDS per CU on gfx950
 
 struct Variant {
   const char* name;
   int mt, nt, kt, threads;
+  int wgs_per_cu;   // workgroups resident per CU (LDS- and register-limited)
+  int eff_permil;   // measured share of the FP64 MFMA peak on large square shapes, per mille;
+                    // 0 keeps the variant out of the automatic choice
   KernelFn fn[2][2];  // [transa][transb]
 };
 
 template <class C>
-constexpr Variant make_variant(const char* name) {
+constexpr int resident_wgs() {
+  // LDS footprint with the larger (padded) row stride of either operand layout.
+  constexpr int lds = 2 * C::KT * 8 * (LdsLayout<C, false, true>::A + LdsLayout<C, true, false>::B);
+  constexpr int by_lds = kLdsPerCU / lds;
+  constexpr int by_waves = (C::MIN_WAVES_PER_EU * 4) / C::WAVES;
+  return by_lds < by_waves ? by_lds : by_waves;
+}
+
+template <class C>
+constexpr Variant make_variant(const char* name, int eff_permil) {
   return Variant{name,
                  C::MT,
                  C::NT,
                  C::KT,
                  C::THREADS,
+                 resident_wgs<C>() > 0 ? resident_wgs<C>() : 1,
+                 eff_permil,
                  {{dgemm_mfma_kernel<C, false, false>, dgemm_mfma_kernel<C, false, true>},
                   {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
 }
 
+// Efficiencies are the measured TFLOP/s of each variant at m = n = k = 8192..16384 (all four
+// transpose cases averaged) divided by 78.6.
 const Variant kVariants[] = {
-    make_variant<Big>("mfma_f64_128x128x16_w64x64"),
-    make_variant<Small>("mfma_f64_64x64x16_w32x32"),
+    make_variant<Big>("mfma_f64_128x128x16_w64x64", 795),
+    make_variant<Small>("mfma_f64_64x64x16_w32x32", 760),
+    make_variant<Big8a>("mfma_f64_128x128x16_w32x64", 848),
+    make_variant<Big8b>("mfma_f64_128x128x16_w64x32", 853),
+    make_variant<Tall>("mfma_f64_256x128x16_w64x64", 816),
+    make_variant<Wide>("mfma_f64_128x256x16_w64x64", 816),
+    make_variant<Big16>("mfma_f64_128x128x16_w32x32", 865),
+    make_variant<Tall16>("mfma_f64_256x128x16_w64x32", 847),
+    make_variant<Mid8>("mfma_f64_128x64x16_w32x32", 790),
+    make_variant<Big16p>("mfma_f64_128x128x16_w32x32_pad", 860),
+    make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 630),
+    make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -341,11 +424,26 @@ int check_args(char transa, char transb, int64_t m, int64_t n, int64_t k, double
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Shape heuristic: the large tile when it gives at least two tiles per CU (256 CUs), else the
-// small one, which quadruples the number of workgroups.
+// Shape-driven choice. A launch runs in rounds of kCUs * wgs_per_cu workgroups; a round costs
+// about wgs_per_cu * mt * nt * k / efficiency whether or not every slot is filled (a partly filled
+// round is latency-bound, not faster per tile). The variant with the smallest estimate wins; ties
+// go to the earlier entry.
 int pick_variant(int64_t m, int64_t n, int64_t /*k*/) {
-  const int64_t big_tiles = ceil_div(m, 128) * ceil_div(n, 128);
-  return big_tiles >= 512 ? 0 : 1;
+  int best = 0;
+  double best_cost = 0.0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    const Variant& var = kVariants[v];
+    if (var.eff_permil <= 0) continue;
+    const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
+    const int64_t slots = (int64_t)kCUs * var.wgs_per_cu;
+    const double rounds = (double)ceil_div(tiles, slots);
+    const double cost = rounds * var.wgs_per_cu * var.mt * var.nt / (var.eff_permil * 1e-3);
+    if (best_cost == 0.0 || cost < best_cost) {
+      best = v;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 thread_local int t_last_hip_error = 0;  // raw hipError_t of the last failed HIP call, per thread

@@ -26,7 +26,7 @@ def _variants():
     return [-1] + list(range(mdg.mdg_num_variants()))
 
 
-VARIANTS = [-1, 0, 1]
+VARIANTS = _variants()
 
 SHAPES = [(1, 1, 1), (1, 17, 3), (17, 1, 5), (5, 7, 1), (16, 16, 4), (64, 64, 16), (65, 63, 17),
           (128, 128, 16), (129, 130, 31), (200, 300, 77), (255, 257, 129), (300, 200, 513)]
@@ -34,10 +34,6 @@ SHAPES = [(1, 1, 1), (1, 17, 3), (17, 1, 5), (5, 7, 1), (16, 16, 4), (64, 64, 16
 
 def _pad3(rows):
     return max(1, rows) + 3
-
-
-def test_variant_list_is_covered():
-    assert sorted(_variants()) == sorted(VARIANTS), "update VARIANTS for new kernel variants"
 
 
 @pytest.mark.parametrize("variant", VARIANTS)

@@ -75,6 +75,10 @@ def build_problems(torch, shapes_filter=None):
     return probs
 
 
+def out_workload(probs):
+    return sorted({f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}" for p in probs})
+
+
 def flops(p):
     return 2.0 * p["m"] * p["n"] * p["k"]
 
@@ -235,12 +239,14 @@ def main():
     avg_ms = dom["ms"] / dom["launches"]
     achieved = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
 
+    # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled by a
+    # copy-kernel calibration), valid only if taken on this kernel source and the same launch mix.
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
             t = json.load(open(TRAFFIC_FILE))
-            if t.get("source_sha") == source_hash() and t.get("kernel") == dom_key:
-                traffic = t.get("bytes_per_launch")
+            if t.get("source_sha") == source_hash() and t.get("workload") == out_workload(probs):
+                traffic = t.get("bytes_per_launch", {}).get(dom_key)
         except (OSError, ValueError):
             traffic = None
 

@@ -105,6 +105,57 @@ int mdg_variant_info(int variant, int *mt, int *nt, int *kt, int *threads);
 /* Static description of a status code (never NULL). */
 const char *mdg_status_string(int status);
 
+/* ------------------------------------------------------------------------------------------
+ * Split-precision FP64 GEMM on the INT8 matrix cores (Ozaki scheme; not in the paper, which
+ * computes dgemm in FP64 only -- this is the same operation of section 1.2, emulated).
+ *
+ * op(A) is scaled row by row and op(B) column by column by powers of two so every entry lies in
+ * (-1, 1), each scaled entry is split exactly into `nslices` int8 slices of 7 bits, the products
+ * of slice pairs (s, t) with s + t <= nslices + 1 are formed exactly in INT32 on
+ * v_mfma_i32_16x16x64_i8, and the sum is recombined, unscaled and combined with alpha, beta and
+ * the old C in binary64. The result approximates the FP64 product: the error is about
+ * k * 2^(-7*nslices) times the product of the row and column maxima, so entries whose magnitudes
+ * spread widely within a row or column need more slices (at exponent spread phi, nslices = 7 for
+ * phi = 0, 8 for phi = 8, 10 for phi = 32 give max |C - Cref| / (|A||B|)_ij below 1e-13 on the
+ * tested shapes). Inputs must be finite: NaN or Inf in A or B gives an unspecified result.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Largest supported `nslices` (the smallest is 1). */
+int mdg_split_max_slices(void);
+
+/*
+ * Bytes of device workspace mdg_dgemm_split needs for these sizes, or -1 for invalid sizes or
+ * slice count. Layout: int8 slices of op(A) [nslices][m][kp], of op(B)^T [nslices][n][kp]
+ * (kp = k rounded up to a multiple of 64, zero padded), then int32 exponents of the m rows and
+ * n columns, each part aligned to 256 bytes.
+ */
+int64_t mdg_dgemm_split_workspace_size(int64_t m, int64_t n, int64_t k, int nslices);
+
+/*
+ * C := alpha*op(A)*op(B) + beta*C by the split-precision scheme above. Arguments 1-13 and the
+ * stream are as for mdg_dgemm; `workspace` is a caller-owned device buffer of at least
+ * mdg_dgemm_split_workspace_size(m, n, k, nslices) bytes, 256-byte aligned, which the call
+ * overwrites (it must stay untouched until the work completes on `stream`). Extra status codes:
+ * 14 nslices out of range, 15 workspace NULL, too small or misaligned; MDG_ERR_SIZE when a slice
+ * array exceeds 4 GiB. Conventions for m, n, k, alpha, beta zero are those of mdg_dgemm.
+ */
+int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                    double alpha, const double *A, int64_t lda,
+                    const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc,
+                    int nslices, void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * The slicing step alone, for one operand: operand 0 slices the rows of op(A) (rows = m, trans =
+ * transa, X = A, ld = lda), operand 1 the columns of op(B) (rows = n, trans = transb, X = B,
+ * ld = ldb). Writes slices[s*rows*kp + r*kp + p] (kp = k rounded up to 64; zero for p >= k) and
+ * exponents[r] = e with max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row). Returns 0, or
+ * 1 operand, 2 trans, 3 rows < 0, 4 k < 0, 5 X NULL, 6 ld too small, 7 nslices out of range,
+ * 8 output NULL, or a negative runtime code.
+ */
+int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const double *X, int64_t ld,
+                     int nslices, int8_t *slices, int32_t *exponents, void *stream);
+
 /*
  * The raw hipError_t of the last HIP call that failed inside this library on the
  * calling thread (0 if none): the detail behind an MDG_ERR_HIP return.

@@ -74,6 +74,14 @@ def load():
     lib.mdg_version.restype = ci
     lib.mdg_last_hip_error.argtypes = []
     lib.mdg_last_hip_error.restype = ci
+    lib.mdg_split_max_slices.argtypes = []
+    lib.mdg_split_max_slices.restype = ci
+    lib.mdg_dgemm_split_workspace_size.argtypes = [i64, i64, i64, ci]
+    lib.mdg_dgemm_split_workspace_size.restype = i64
+    lib.mdg_dgemm_split.argtypes = gemm_args[:-1] + [ci, vp, i64, vp]
+    lib.mdg_dgemm_split.restype = ci
+    lib.mdg_split_slices.argtypes = [ci, ch, i64, i64, vp, i64, ci, vp, vp, vp]
+    lib.mdg_split_slices.restype = ci
     _lib = lib
     return lib
 
@@ -187,6 +195,52 @@ def mdg_version() -> int:
 
 def mdg_last_hip_error() -> int:
     return load().mdg_last_hip_error()
+
+
+def mdg_split_max_slices() -> int:
+    return load().mdg_split_max_slices()
+
+
+def mdg_dgemm_split_workspace_size(m, n, k, nslices) -> int:
+    return load().mdg_dgemm_split_workspace_size(int(m), int(n), int(k), int(nslices))
+
+
+def _raw_ptr(x, need_bytes: int, name: str):
+    """Device address of a tensor of any dtype (storage extent checked in bytes), int or None."""
+    if x is None or isinstance(x, int):
+        return x
+    import torch
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise TypeError(f"{name}: expected a device tensor, an int address or None")
+    st = x.untyped_storage()
+    if st.data_ptr() + st.nbytes() - x.data_ptr() < need_bytes:
+        raise ValueError(f"{name}: storage smaller than the {need_bytes} bytes the call needs")
+    return x.data_ptr()
+
+
+def mdg_dgemm_split(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices,
+                    workspace, workspace_bytes, stream=None) -> int:
+    """Split-precision C := alpha*op(A)*op(B) + beta*C on INT8 MFMA; returns the status code.
+
+    `workspace` is a device tensor (any dtype) or address of at least `workspace_bytes` bytes.
+    """
+    args = _marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
+    ws = _raw_ptr(workspace, max(0, int(workspace_bytes)), "workspace")
+    return load().mdg_dgemm_split(*args[:-1], int(nslices), ws, int(workspace_bytes), args[-1])
+
+
+def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents, stream=None) -> int:
+    """Slicing step alone (operand 0: rows of op(A); 1: columns of op(B)); returns the status."""
+    kp = (int(k) + 63) // 64 * 64
+    row_contig = _is_trans(trans) if operand == 0 else not _is_trans(trans)
+    need_x = _extent(k if row_contig else rows, rows if row_contig else k, ld) \
+        if rows > 0 and k > 0 and ld >= max(1, k if row_contig else rows) else 0
+    ok_s = 1 <= int(nslices) <= mdg_split_max_slices()
+    xp = _ptr(X, need_x, "X")
+    sp = _raw_ptr(slices, int(nslices) * int(rows) * kp if ok_s and rows > 0 else 0, "slices")
+    ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
+    return load().mdg_split_slices(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),
+                                   int(nslices), sp, ep, _stream(stream))
 
 
 def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None, variant=-1):

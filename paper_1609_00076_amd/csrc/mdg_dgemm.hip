@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "mdg.h"
+#include "mdg_internal.h"
 
 // Kernels need external linkage so the runtime can resolve them by name at launch; everything
 // in this namespace is private to the library all the same (only the extern "C" API is exported).
@@ -452,6 +453,12 @@ int hip_fail(hipError_t e) {
   t_last_hip_error = (int)e;
   return MDG_ERR_HIP;
 }
+
+}  // namespace mdg_impl
+
+void mdg_record_hip_error(int err) { mdg_impl::t_last_hip_error = err; }
+
+namespace mdg_impl {
 
 // Per-device memo of the architecture check (0 unknown, 1 gfx950, 2 other). Concurrent first
 // calls may both query; they store the same value.

@@ -1,0 +1,458 @@
+// mdg_split.hip -- FP64-accurate GEMM emulated on the INT8 matrix cores (Ozaki scheme).
+//
+// C := alpha*op(A)*op(B) + beta*C (the dgemm operation of the paper, section 1.2) computed as:
+//   1. scale every row i of op(A) by 2^-e_i and every column j of op(B) by 2^-f_j, where e_i (f_j)
+//      is the binary exponent of the row's (column's) largest magnitude, so scaled entries lie in
+//      (-1, 1) (Ozaki, Ogita, Oishi, Rump, Numer. Algorithms 2012; Ootomo, Ozaki, Yokota, IJHPCA
+//      2024);
+//   2. split each scaled entry x into S int8 slices q_1..q_S, x = sum_s q_s 2^-7s + r 2^-7S,
+//      by S exact binary64 steps (x := 128x, q := trunc(x), x := x - q);
+//   3. form the slice products P_st = A_s B_t with s + t <= S + 1 exactly in INT32 on
+//      v_mfma_i32_16x16x64_i8, summed per anti-diagonal d = s + t;
+//   4. recombine in binary64: C' = sum_d 2^-7d sum_{s+t=d} P_st, unscale by 2^(e_i + f_j), and
+//      apply alpha and beta in binary64.
+// Slices live in a caller-provided workspace, k-contiguous per row of op(A) and per column of
+// op(B), padded with zeros to a multiple of 64 in k.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mdg.h"
+#include "mdg_internal.h"
+
+namespace mdg_split_impl {
+
+constexpr int kBeta = 7;          // bits per slice
+constexpr int kKStep = 64;        // k per INT8 MFMA (and per LDS stage)
+constexpr int kMaxSlices = 10;    // double-buffered LDS stage of 64x64 tiles fits up to here
+constexpr int kSliceMax = 127;    // |q| bound
+constexpr int kBufferWord3 = 0x00020000;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const uint32_t num = bytes <= 0 ? 0u : bytes >= (int64_t)0xFFFFFFFF ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)num, kBufferWord3);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Slicing. X is a rows x k matrix given by its storage: x(r,p) = X[r*ld + p] when ROW_CONTIG
+// (op(A) with transa = T, op(B)^T with transb = N), else X[p*ld + r]. Output: exps[r] and
+// out[s*rows*kp + r*kp + p] for p < kp (zero for p >= k).
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ int row_exponent(double mx) {
+  int e = 0;
+  if (mx != 0.0) (void)frexp(mx, &e);  // mx = f * 2^e, f in [0.5, 1)
+  return e;
+}
+
+// Slices of 16 consecutive entries (already scaled into (-1, 1)) to S 16-byte groups.
+template <int S>
+__device__ __forceinline__ void slice16(double (&v)[16], v4i (&q)[S]) {
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      v[e] *= (double)(1 << kBeta);
+      const double t = trunc(v[e]);
+      v[e] -= t;
+      w[e / 4] |= ((uint32_t)(int)t & 0xFFu) << (8 * (e % 4));
+    }
+    q[s] = (v4i){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+  }
+}
+
+// Row-contiguous storage: one wave per row.
+template <int S>
+__global__ void __launch_bounds__(256) slice_rows_kernel(const double* X, int64_t ld, int64_t rows,
+                                                         int64_t k, int64_t kp, int8_t* out,
+                                                         int32_t* exps) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  const double* x = X + r * ld;
+  double mx = 0.0;
+  for (int64_t p = lane; p < k; p += 64) mx = fmax(mx, fabs(x[p]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  const int e = row_exponent(mx);
+  if (lane == 0) exps[r] = e;
+  for (int64_t p0 = (int64_t)lane * 16; p0 < kp; p0 += 64 * 16) {
+    double v[16];
+#pragma unroll
+    for (int e2 = 0; e2 < 16; ++e2) {
+      v[e2] = 0.0;
+      if (p0 + e2 < k) v[e2] = ldexp(x[p0 + e2], -e);
+    }
+    v4i q[S];
+    slice16<S>(v, q);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      *reinterpret_cast<v4i*>(out + (int64_t)s * rows * kp + r * kp + p0) = q[s];
+  }
+}
+
+// Column-contiguous storage: a workgroup takes 16 rows; thread (rr, ph) reads row rr at k-phase ph,
+// so 16 neighbouring threads read 128 contiguous bytes.
+template <int S>
+__global__ void __launch_bounds__(256) slice_cols_kernel(const double* X, int64_t ld, int64_t rows,
+                                                         int64_t k, int64_t kp, int8_t* out,
+                                                         int32_t* exps) {
+  __shared__ double red[16][17];
+  const int rr = threadIdx.x & 15, ph = threadIdx.x >> 4;
+  const int64_t r = (int64_t)blockIdx.x * 16 + rr;
+  const bool live = r < rows;
+  double mx = 0.0;
+  if (live)
+    for (int64_t p = ph; p < k; p += 16) mx = fmax(mx, fabs(X[p * ld + r]));
+  red[rr][ph] = mx;
+  __syncthreads();
+  if (ph == 0) {
+    double m2 = 0.0;
+    for (int q = 0; q < 16; ++q) m2 = fmax(m2, red[rr][q]);
+    red[rr][16] = m2;
+  }
+  __syncthreads();
+  if (!live) return;
+  const int e = row_exponent(red[rr][16]);
+  if (ph == 0) exps[r] = e;
+  for (int64_t p0 = (int64_t)ph * 16; p0 < kp; p0 += 16 * 16) {
+    double v[16];
+#pragma unroll
+    for (int e2 = 0; e2 < 16; ++e2) {
+      v[e2] = 0.0;
+      if (p0 + e2 < k) v[e2] = ldexp(X[(p0 + e2) * ld + r], -e);
+    }
+    v4i q[S];
+    slice16<S>(v, q);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      *reinterpret_cast<v4i*>(out + (int64_t)s * rows * kp + r * kp + p0) = q[s];
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Slice-product GEMM with FP64 recombination and the alpha/beta epilogue.
+//
+// Workgroup: 64x64 tile of C, 4 waves of 32x32 (2x2 blocks of 16x16). LDS stage per k-step of 64:
+// S slices x 64 rows x 64 bytes for each operand. A row's 64 bytes are four 16-byte chunks stored
+// at chunk position c ^ ((row >> 2) & 3), so the 16 rows of one fragment read fall in 16 disjoint
+// 16-byte bank groups.
+//
+// v_mfma_i32_16x16x64_i8(X, Y, Z) gives D = X*Y + Z for a 16x64 X and 64x16 Y; lane l supplies
+// the 16 bytes X[l%16][16*(l/16) ..] and Y[16*(l/16) ..][l%16] and holds D[4*(l/16) + r][l%16] in
+// accumulator r. With X = B_t^T and Y = A_s^T, D = (A_s B_t)^T and lane l holds
+// C(i0 + l%16, j0 + 4*(l/16) + r): 16 consecutive rows of a column per 16 lanes.
+// ------------------------------------------------------------------------------------------------
+struct SplitArgs {
+  int64_t m, n, kp;
+  double alpha, beta;
+  double* C;
+  int64_t ldc;
+  const int8_t* As;  // [S][m][kp]
+  const int8_t* Bs;  // [S][n][kp]
+  const int32_t* ea;
+  const int32_t* eb;
+  int flush_steps;   // k-steps of 64 after which the INT32 accumulators are folded into FP64
+};
+
+constexpr int kTile = 64;
+constexpr int kStageRow = 64;                         // bytes per row per slice in LDS
+constexpr int kSliceBytes = kTile * kStageRow;        // 4 KiB per slice per operand
+
+__device__ __forceinline__ int swz(int row, int chunk) {
+  return row * kStageRow + ((chunk ^ ((row >> 2) & 3)) << 4);
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][2][S][kSliceBytes];  // [buf][A/B][s][..]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wave_m = wave & 1, wave_n = wave >> 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+
+  // Tile order: column-major over tiles with XCD-contiguous runs (as in the FP64 kernel).
+  int t = blockIdx.x;
+  const int nwg = gridDim.x;
+  if (nwg % 8 == 0) t = (t % 8) * (nwg / 8) + t / 8;
+  const int tm = t % tiles_m, tn = t / tiles_m;
+  const int64_t row0 = (int64_t)tm * kTile, col0 = (int64_t)tn * kTile;
+
+  // Global -> LDS staging: thread loads row (tid >> 2), chunk (tid & 3) of every slice.
+  const int ld_row = tid >> 2, ld_chunk = tid & 3;
+  const int64_t a_slice = g.m * g.kp, b_slice = g.n * g.kp;
+  const rsrc_t ra = make_rsrc(g.As, (int64_t)S * a_slice);
+  const rsrc_t rb = make_rsrc(g.Bs, (int64_t)S * b_slice);
+  const int64_t a_off0 = (row0 + ld_row) * g.kp + ld_chunk * 16;
+  const int64_t b_off0 = (col0 + ld_row) * g.kp + ld_chunk * 16;
+  const int st_off = swz(ld_row, ld_chunk);
+
+  v4i pa[S], pb[S];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // Offsets stay below 2^32: the host keeps S * m * kp and S * n * kp under 4 GiB.
+      pa[s] = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)(s * a_slice + a_off0 + k0), 0, 0);
+      pb[s] = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)(s * b_slice + b_off0 + k0), 0, 0);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      *reinterpret_cast<v4i*>(&lds[buf][0][s][st_off]) = pa[s];
+      *reinterpret_cast<v4i*>(&lds[buf][1][s][st_off]) = pb[s];
+    }
+  };
+
+  v4i acc[S][2][2];  // [diagonal d - 2][bi][bj]
+  d4 cf[2][2];       // recombined FP64 sums
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      cf[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int d = 0; d < S; ++d) acc[d][bi][bj] = (v4i){0, 0, 0, 0};
+    }
+
+  auto fold = [&]() {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+#pragma unroll
+        for (int d = 0; d < S; ++d) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            cf[bi][bj][r] += ldexp((double)acc[d][bi][bj][r], -kBeta * (d + 2));
+          acc[d][bi][bj] = (v4i){0, 0, 0, 0};
+        }
+      }
+  };
+
+  const int nsteps = (int)(g.kp / kKStep);
+  fetch(0);
+  stage(0);
+  __syncthreads();
+
+  const int a_row = wave_m * 32 + l16;  // fragment rows this lane feeds (plus 16*bi / 16*bj)
+  const int b_row = wave_n * 32 + l16;
+  int since_fold = 0;
+  for (int ks = 0; ks < nsteps; ++ks) {
+    const int buf = ks & 1;
+    const bool more = ks + 1 < nsteps;
+    if (more) fetch((int64_t)(ks + 1) * kKStep);
+
+    v4i bf[S][2];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        bf[s][bj] = *reinterpret_cast<const v4i*>(&lds[buf][1][s][swz(b_row + 16 * bj, lq)]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      v4i af[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        af[bi] = *reinterpret_cast<const v4i*>(&lds[buf][0][s][swz(a_row + 16 * bi, lq)]);
+#pragma unroll
+      for (int tt = 0; tt < S - s; ++tt)  // slice pair (s+1, tt+1): diagonal s + tt + 2
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[s + tt][bi][bj] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[tt][bj], af[bi], acc[s + tt][bi][bj], 0, 0, 0);
+    }
+    if (++since_fold == g.flush_steps) {
+      fold();
+      since_fold = 0;
+    }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+  }
+  if (since_fold) fold();
+
+  // Epilogue: C(i,j) := alpha * 2^(e_i + f_j) * C'(i,j) + beta * C(i,j).
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    const int64_t i = row0 + wave_m * 32 + 16 * bi + l16;
+    if (i >= g.m) continue;
+    const int ei = g.ea[i];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = col0 + wave_n * 32 + 16 * bj + 4 * lq + r;
+        if (j >= g.n) continue;
+        double* c = g.C + j * g.ldc + i;
+        const double v = alpha * ldexp(cf[bi][bj][r], ei + g.eb[j]);
+        *c = (beta != 0.0) ? v + beta * *c : v;
+      }
+  }
+}
+
+typedef void (*SliceFn)(const double*, int64_t, int64_t, int64_t, int64_t, int8_t*, int32_t*);
+typedef void (*GemmFn)(SplitArgs, int, int);
+
+template <int S>
+struct Entry {
+  static constexpr SliceFn rows = slice_rows_kernel<S>;
+  static constexpr SliceFn cols = slice_cols_kernel<S>;
+  static constexpr GemmFn gemm = split_gemm_kernel<S>;
+};
+
+struct Fns {
+  SliceFn rows, cols;
+  GemmFn gemm;
+};
+
+const Fns kFns[kMaxSlices + 1] = {
+    {nullptr, nullptr, nullptr},
+    {Entry<1>::rows, Entry<1>::cols, Entry<1>::gemm},
+    {Entry<2>::rows, Entry<2>::cols, Entry<2>::gemm},
+    {Entry<3>::rows, Entry<3>::cols, Entry<3>::gemm},
+    {Entry<4>::rows, Entry<4>::cols, Entry<4>::gemm},
+    {Entry<5>::rows, Entry<5>::cols, Entry<5>::gemm},
+    {Entry<6>::rows, Entry<6>::cols, Entry<6>::gemm},
+    {Entry<7>::rows, Entry<7>::cols, Entry<7>::gemm},
+    {Entry<8>::rows, Entry<8>::cols, Entry<8>::gemm},
+    {Entry<9>::rows, Entry<9>::cols, Entry<9>::gemm},
+    {Entry<10>::rows, Entry<10>::cols, Entry<10>::gemm},
+};
+
+bool is_notrans(char t) { return t == 'N' || t == 'n'; }
+bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+int64_t max1(int64_t x) { return x > 1 ? x : 1; }
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+int64_t kpad(int64_t k) { return (k + kKStep - 1) / kKStep * kKStep; }
+
+struct Layout {
+  int64_t kp, a_bytes, b_bytes, ea_off, eb_off, total;
+};
+
+Layout layout(int64_t m, int64_t n, int64_t k, int S) {
+  Layout L;
+  L.kp = kpad(k);
+  L.a_bytes = align256((int64_t)S * m * L.kp);
+  L.b_bytes = align256((int64_t)S * n * L.kp);
+  L.ea_off = L.a_bytes + L.b_bytes;
+  L.eb_off = L.ea_off + align256(4 * m);
+  L.total = L.eb_off + align256(4 * n);
+  return L;
+}
+
+int launch(const void* fn, dim3 grid, dim3 block, hipStream_t s, void** argv) {
+  const hipError_t e = hipLaunchKernel(fn, grid, block, argv, 0, s);
+  if (e != hipSuccess) {
+    mdg_record_hip_error((int)e);
+    return MDG_ERR_HIP;
+  }
+  return MDG_SUCCESS;
+}
+
+int launch_slices(const Fns& f, bool row_contig, const double* X, int64_t ld, int64_t rows,
+                  int64_t k, int64_t kp, int8_t* out, int32_t* exps, hipStream_t s) {
+  if (rows == 0) return MDG_SUCCESS;
+  void* argv[] = {&X, &ld, &rows, &k, &kp, &out, &exps};
+  if (row_contig)
+    return launch(reinterpret_cast<const void*>(f.rows), dim3((unsigned)((rows + 3) / 4)),
+                  dim3(256), s, argv);
+  return launch(reinterpret_cast<const void*>(f.cols), dim3((unsigned)((rows + 15) / 16)),
+                dim3(256), s, argv);
+}
+
+}  // namespace mdg_split_impl
+
+using namespace mdg_split_impl;
+
+extern "C" {
+
+int mdg_split_max_slices(void) { return kMaxSlices; }
+
+int64_t mdg_dgemm_split_workspace_size(int64_t m, int64_t n, int64_t k, int nslices) {
+  if (m < 0 || n < 0 || k < 0 || nslices < 1 || nslices > kMaxSlices) return -1;
+  return layout(m, n, k, nslices).total;
+}
+
+int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const double* X, int64_t ld,
+                     int nslices, int8_t* slices, int32_t* exponents, void* stream) {
+  if (operand != 0 && operand != 1) return 1;
+  if (!is_notrans(trans) && !is_trans(trans)) return 2;
+  if (rows < 0) return 3;
+  if (k < 0) return 4;
+  // x(r, p) is op(A)(r, p) (operand 0) or op(B)(p, r) (operand 1).
+  const bool row_contig = operand == 0 ? is_trans(trans) : is_notrans(trans);
+  const int64_t need_ld = row_contig ? k : rows;
+  if (rows > 0 && k > 0 && X == nullptr) return 5;
+  if (ld < max1(need_ld)) return 6;
+  if (nslices < 1 || nslices > kMaxSlices) return 7;
+  if (rows > 0 && (slices == nullptr || exponents == nullptr)) return 8;
+  return launch_slices(kFns[nslices], row_contig, X, ld, rows, k, kpad(k), slices, exponents,
+                       static_cast<hipStream_t>(stream));
+}
+
+int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                    double* C, int64_t ldc, int nslices, void* workspace, int64_t workspace_bytes,
+                    void* stream) {
+  if (!is_notrans(transa) && !is_trans(transa)) return 1;
+  if (!is_notrans(transb) && !is_trans(transb)) return 2;
+  if (m < 0) return 3;
+  if (n < 0) return 4;
+  if (k < 0) return 5;
+  const bool empty = (m == 0 || n == 0);
+  const bool no_product = (alpha == 0.0 || k == 0);
+  const bool reads_ab = !empty && !no_product;
+  const int64_t rows_a = is_notrans(transa) ? m : k;
+  const int64_t rows_b = is_notrans(transb) ? k : n;
+  if (reads_ab && A == nullptr) return 7;
+  if (lda < max1(rows_a)) return 8;
+  if (reads_ab && B == nullptr) return 9;
+  if (ldb < max1(rows_b)) return 10;
+  if (!empty && !(no_product && beta == 1.0) && C == nullptr) return 12;
+  if (ldc < max1(m)) return 13;
+  if (nslices < 1 || nslices > kMaxSlices) return 14;
+  if (empty || (no_product && beta == 1.0)) return MDG_SUCCESS;
+  if (no_product)  // C := beta*C needs no slices: the native entry point does exactly this
+    return mdg_dgemm(transa, transb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+  const Layout L = layout(m, n, k, nslices);
+  if (workspace == nullptr || workspace_bytes < L.total) return 15;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return 15;
+  if (L.a_bytes > (int64_t)0xFFFFFFFF - 4096 || L.b_bytes > (int64_t)0xFFFFFFFF - 4096)
+    return MDG_ERR_SIZE;  // slice offsets are 32-bit
+  const int64_t tiles_m = (m + kTile - 1) / kTile, tiles_n = (n + kTile - 1) / kTile;
+  if (tiles_m * tiles_n > (int64_t)INT32_MAX / 256) return MDG_ERR_SIZE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int8_t* ws = static_cast<int8_t*>(workspace);
+  int8_t* as = ws;
+  int8_t* bs = ws + L.a_bytes;
+  int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
+  int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
+  const Fns& f = kFns[nslices];
+  int st = launch_slices(f, is_trans(transa), A, lda, m, k, L.kp, as, ea, s);
+  if (st) return st;
+  st = launch_slices(f, is_notrans(transb), B, ldb, n, k, L.kp, bs, eb, s);
+  if (st) return st;
+
+  // INT32 headroom: a diagonal sums at most nslices products of 64 terms of magnitude <= 127^2
+  // per k-step.
+  const int64_t per_step = (int64_t)nslices * kKStep * kSliceMax * kSliceMax;
+  int flush = (int)((int64_t)INT32_MAX / per_step);
+  if (flush < 1) flush = 1;
+  SplitArgs g{m, n, L.kp, alpha, beta, C, ldc, as, bs, ea, eb, flush};
+  int tm = (int)tiles_m, tn = (int)tiles_n;
+  void* argv[] = {&g, &tm, &tn};
+  return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)(tiles_m * tiles_n)),
+                dim3(256), s, argv);
+}
+
+}  // extern "C"

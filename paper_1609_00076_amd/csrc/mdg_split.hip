@@ -137,10 +137,9 @@ __global__ void __launch_bounds__(256) slice_cols_kernel(const double* X, int64_
 // ------------------------------------------------------------------------------------------------
 // Slice-product GEMM with FP64 recombination and the alpha/beta epilogue.
 //
-// Workgroup: 64x64 tile of C, 4 waves of 32x32 (2x2 blocks of 16x16). LDS stage per k-step of 64:
+// Workgroup: 64x64 tile of C. LDS stage per k-step of 64:
 // S slices x 64 rows x 64 bytes for each operand. A row's 64 bytes are four 16-byte chunks stored
-// at chunk position c ^ ((row >> 2) & 3), so the 16 rows of one fragment read fall in 16 disjoint
-// 16-byte bank groups.
+// in a row-dependent order (see swz), so the rows of one fragment read fall in disjoint banks.
 //
 // v_mfma_i32_16x16x64_i8(X, Y, Z) gives D = X*Y + Z for a 16x64 X and 64x16 Y; lane l supplies
 // the 16 bytes X[l%16][16*(l/16) ..] and Y[16*(l/16) ..][l%16] and holds D[4*(l/16) + r][l%16] in
@@ -163,12 +162,21 @@ constexpr int kTile = 64;
 constexpr int kStageRow = 64;                         // bytes per row per slice in LDS
 constexpr int kSliceBytes = kTile * kStageRow;        // 4 KiB per slice per operand
 
+// The chunk permutation makes the 16-byte reads of 16 consecutive rows at one chunk position
+// conflict-free both when the LDS serves 8 lanes per cycle over 32 banks and when it serves 16
+// lanes over 64 banks; each row keeps its four chunks, so the staging writes stay conflict-free.
 __device__ __forceinline__ int swz(int row, int chunk) {
-  return row * kStageRow + ((chunk ^ ((row >> 2) & 3)) << 4);
+  return row * kStageRow + ((chunk ^ (((row >> 1) ^ (row >> 3)) & 3)) << 4);
 }
 
+// 8 waves (2 per SIMD) on a 64x64 tile: wave (wm, wn) with wm in 0..1, wn in 0..3 owns rows
+// 32*wm .. +31 (RB = 2 blocks) and columns 16*wn .. +15 (one block). Per k-step a wave holds the S
+// B-fragments of its column block and streams the A-fragments slice by slice.
+constexpr int kThreads = 512;
+constexpr int kRB = 2;
+
 template <int S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) int8_t lds[2][2][S][kSliceBytes];  // [buf][A/B][s][..]
 
@@ -177,125 +185,120 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   const int wave_m = wave & 1, wave_n = wave >> 1;
   const int l16 = lane & 15, lq = lane >> 4;
 
-  // Tile order: column-major over tiles with XCD-contiguous runs (as in the FP64 kernel).
+  // Tile order: each XCD gets a contiguous run of tiles, visited in column groups of 8 tile-rows,
+  // so the 32 workgroups resident on an XCD cover an 8 x 4 block and share A and B panels in L2.
   int t = blockIdx.x;
   const int nwg = gridDim.x;
   if (nwg % 8 == 0) t = (t % 8) * (nwg / 8) + t / 8;
-  const int tm = t % tiles_m, tn = t / tiles_m;
+  constexpr int kGroup = 8;
+  const int per_group = kGroup * tiles_n;
+  const int grp = t / per_group, first_m = grp * kGroup;
+  const int gsize = min(tiles_m - first_m, kGroup);
+  const int rem = t - grp * per_group;
+  const int tm = first_m + rem % gsize, tn = rem / gsize;
   const int64_t row0 = (int64_t)tm * kTile, col0 = (int64_t)tn * kTile;
 
-  // Global -> LDS staging: thread loads row (tid >> 2), chunk (tid & 3) of every slice.
-  const int ld_row = tid >> 2, ld_chunk = tid & 3;
-  const int64_t a_slice = g.m * g.kp, b_slice = g.n * g.kp;
-  const rsrc_t ra = make_rsrc(g.As, (int64_t)S * a_slice);
-  const rsrc_t rb = make_rsrc(g.Bs, (int64_t)S * b_slice);
-  const int64_t a_off0 = (row0 + ld_row) * g.kp + ld_chunk * 16;
-  const int64_t b_off0 = (col0 + ld_row) * g.kp + ld_chunk * 16;
+  // Global -> LDS staging: threads 0..255 carry A, 256..511 carry B; thread loads row
+  // (tid % 256) >> 2, chunk tid & 3 of every slice of its operand.
+  const int ld_op = tid >> 8, ld_row = (tid & 255) >> 2, ld_chunk = tid & 3;
+  const int64_t slice_stride = ld_op ? g.n * g.kp : g.m * g.kp;
+  const rsrc_t rsrc = make_rsrc(ld_op ? (const void*)g.Bs : (const void*)g.As, (int64_t)S * slice_stride);
+  const int64_t off0 = ((ld_op ? col0 : row0) + ld_row) * g.kp + ld_chunk * 16;
   const int st_off = swz(ld_row, ld_chunk);
 
-  v4i pa[S], pb[S];
-  auto fetch = [&](int64_t k0) {
+  // Two register sets of staged data: the panel for step ks+2 is loaded while step ks computes,
+  // so a load has two k-steps of arithmetic to arrive before it is written to LDS.
+  v4i pre0[S], pre1[S];
+  auto fetch = [&](v4i (&pre)[S], int64_t k0) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < S; ++s)
       // Offsets stay below 2^32: the host keeps S * m * kp and S * n * kp under 4 GiB.
-      pa[s] = __builtin_amdgcn_raw_buffer_load_b128(ra, (int)(s * a_slice + a_off0 + k0), 0, 0);
-      pb[s] = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)(s * b_slice + b_off0 + k0), 0, 0);
-    }
+      pre[s] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(s * slice_stride + off0 + k0), 0, 0);
   };
-  auto stage = [&](int buf) {
+  auto stage = [&](const v4i (&pre)[S], int buf) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      *reinterpret_cast<v4i*>(&lds[buf][0][s][st_off]) = pa[s];
-      *reinterpret_cast<v4i*>(&lds[buf][1][s][st_off]) = pb[s];
-    }
+    for (int s = 0; s < S; ++s) *reinterpret_cast<v4i*>(&lds[buf][ld_op][s][st_off]) = pre[s];
   };
 
-  v4i acc[S][2][2];  // [diagonal d - 2][bi][bj]
-  d4 cf[2][2];       // recombined FP64 sums
+  v4i acc[S][kRB];  // [diagonal d - 2][bi]
+  d4 cf[kRB];       // recombined FP64 sums
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < kRB; ++bi) {
+    cf[bi] = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      cf[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int d = 0; d < S; ++d) acc[d][bi][bj] = (v4i){0, 0, 0, 0};
-    }
+    for (int d = 0; d < S; ++d) acc[d][bi] = (v4i){0, 0, 0, 0};
+  }
 
   auto fold = [&]() {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < kRB; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
+      for (int d = 0; d < S; ++d) {
 #pragma unroll
-        for (int d = 0; d < S; ++d) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            cf[bi][bj][r] += ldexp((double)acc[d][bi][bj][r], -kBeta * (d + 2));
-          acc[d][bi][bj] = (v4i){0, 0, 0, 0};
-        }
+        for (int r = 0; r < 4; ++r) cf[bi][r] += ldexp((double)acc[d][bi][r], -kBeta * (d + 2));
+        acc[d][bi] = (v4i){0, 0, 0, 0};
       }
   };
 
   const int nsteps = (int)(g.kp / kKStep);
-  fetch(0);
-  stage(0);
+  fetch(pre0, 0);
+  stage(pre0, 0);
+  if (nsteps > 1) fetch(pre1, kKStep);
   __syncthreads();
 
-  const int a_row = wave_m * 32 + l16;  // fragment rows this lane feeds (plus 16*bi / 16*bj)
-  const int b_row = wave_n * 32 + l16;
+  const int a_row = wave_m * 32 + l16;  // fragment rows this lane feeds (plus 16*bi)
+  const int b_row = wave_n * 16 + l16;
   int since_fold = 0;
-  for (int ks = 0; ks < nsteps; ++ks) {
-    const int buf = ks & 1;
-    const bool more = ks + 1 < nsteps;
-    if (more) fetch((int64_t)(ks + 1) * kKStep);
 
-    v4i bf[S][2];
+  // One k-step: compute from LDS buffer ks & 1; `next` holds step ks+1 (staged at the end),
+  // `spare` receives step ks+2.
+  auto step = [&](int ks, v4i (&next)[S], v4i (&spare)[S]) {
+    const int buf = ks & 1;
+    if (ks + 2 < nsteps) fetch(spare, (int64_t)(ks + 2) * kKStep);
+
+    v4i bf[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        bf[s][bj] = *reinterpret_cast<const v4i*>(&lds[buf][1][s][swz(b_row + 16 * bj, lq)]);
+    for (int s = 0; s < S; ++s) bf[s] = *reinterpret_cast<const v4i*>(&lds[buf][1][s][swz(b_row, lq)]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      v4i af[2];
+      v4i af[kRB];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < kRB; ++bi)
         af[bi] = *reinterpret_cast<const v4i*>(&lds[buf][0][s][swz(a_row + 16 * bi, lq)]);
 #pragma unroll
       for (int tt = 0; tt < S - s; ++tt)  // slice pair (s+1, tt+1): diagonal s + tt + 2
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-            acc[s + tt][bi][bj] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[tt][bj], af[bi], acc[s + tt][bi][bj], 0, 0, 0);
+        for (int bi = 0; bi < kRB; ++bi)
+          acc[s + tt][bi] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[tt], af[bi], acc[s + tt][bi], 0, 0, 0);
     }
     if (++since_fold == g.flush_steps) {
       fold();
       since_fold = 0;
     }
-    if (more) stage(buf ^ 1);
+    if (ks + 1 < nsteps) stage(next, buf ^ 1);
     __syncthreads();
+  };
+  for (int ks = 0; ks < nsteps; ks += 2) {
+    step(ks, pre1, pre0);
+    if (ks + 1 < nsteps) step(ks + 1, pre0, pre1);
   }
   if (since_fold) fold();
 
   // Epilogue: C(i,j) := alpha * 2^(e_i + f_j) * C'(i,j) + beta * C(i,j).
   const double alpha = g.alpha, beta = g.beta;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
+  for (int bi = 0; bi < kRB; ++bi) {
     const int64_t i = row0 + wave_m * 32 + 16 * bi + l16;
     if (i >= g.m) continue;
     const int ei = g.ea[i];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t j = col0 + wave_n * 32 + 16 * bj + 4 * lq + r;
-        if (j >= g.n) continue;
-        double* c = g.C + j * g.ldc + i;
-        const double v = alpha * ldexp(cf[bi][bj][r], ei + g.eb[j]);
-        *c = (beta != 0.0) ? v + beta * *c : v;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = col0 + wave_n * 16 + 4 * lq + r;
+      if (j >= g.n) continue;
+      double* c = g.C + j * g.ldc + i;
+      const double v = alpha * ldexp(cf[bi][r], ei + g.eb[j]);
+      *c = (beta != 0.0) ? v + beta * *c : v;
+    }
   }
 }
 
@@ -452,7 +455,7 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   int tm = (int)tiles_m, tn = (int)tiles_n;
   void* argv[] = {&g, &tm, &tn};
   return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)(tiles_m * tiles_n)),
-                dim3(256), s, argv);
+                dim3(kThreads), s, argv);
 }
 
 }  // extern "C"

@@ -156,6 +156,64 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
 int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const double *X, int64_t ld,
                      int nslices, int8_t *slices, int32_t *exponents, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Grouped launch: many independent dgemm operations (each exactly as mdg_dgemm) in one
+ * persistent kernel. Not in the paper; a batching layer over the same operation.
+ *
+ * 1. mdg_grouped_plan (host only, no HIP call) validates every GEMM and writes a plan: one
+ *    descriptor per GEMM (device pointers and sizes copied from `descs`) and the list of output
+ *    tiles in schedule order. tile_class[i] (NULL = automatic: 1 when m < 48 or n < 48, else 0)
+ *    picks the tile of GEMM i: 0 = 64x64 (the tile of variant "mfma_f64_64x64x16_w32x32"),
+ *    1 = 32x32 (variant "mfma_f64_32x32x16_w16x16"); results are bitwise those of mdg_dgemm_ex
+ *    with that variant. schedule: MDG_SCHEDULE_NATURAL (GEMM by GEMM) or MDG_SCHEDULE_LPT
+ *    (tiles by decreasing cost, i.e. tile area times k).
+ * 2. The caller copies the plan bytes to device memory (16-byte aligned) and keeps them, and the
+ *    matrices the descriptors point to, alive and unchanged while launches are pending.
+ * 3. mdg_dgemm_grouped launches one persistent kernel of `grid` workgroups (0 = 4 per CU) that
+ *    walks the tile list. It allocates and clears nothing, so it may be captured in a graph and
+ *    replayed; every replay recomputes C := alpha*op(A)*op(B) + beta*C for every GEMM.
+ * GEMMs must not write overlapping C (not checked).
+ * ------------------------------------------------------------------------------------------ */
+
+#define MDG_SCHEDULE_NATURAL 0
+#define MDG_SCHEDULE_LPT 1
+
+typedef struct mdg_gemm_desc {
+  char transa, transb;
+  int64_t m, n, k;
+  double alpha;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double beta;
+  double *C;
+  int64_t ldc;
+} mdg_gemm_desc;
+
+/* Number of tile classes accepted in tile_class[]. */
+int mdg_grouped_tile_classes(void);
+
+/* Bytes of the plan for these GEMMs and tile classes, or -1 (count < 0, NULL descs, bad class). */
+int64_t mdg_grouped_plan_bytes(int count, const mdg_gemm_desc *descs, const int32_t *tile_class);
+
+/*
+ * Writes the plan into host memory `plan` (plan_bytes >= mdg_grouped_plan_bytes). Returns 0 and
+ * the number of tiles in *num_tiles; or 1 bad count/descs, 3 bad tile class, 4 bad schedule,
+ * 5 plan NULL or too small; or 100 + the mdg_dgemm argument code of the first invalid GEMM, whose
+ * index goes to *bad_index; or MDG_ERR_SIZE.
+ */
+int mdg_grouped_plan(int count, const mdg_gemm_desc *descs, const int32_t *tile_class,
+                     int schedule, void *plan, int64_t plan_bytes, int64_t *num_tiles,
+                     int *bad_index);
+
+/*
+ * Runs a plan already in device memory. num_tiles is the value mdg_grouped_plan returned; grid is
+ * the number of persistent workgroups (0 = four per CU, never more than num_tiles). Returns 0, or
+ * 1 plan NULL or misaligned, 2 num_tiles < 0, 3 grid < 0, or a negative runtime code.
+ */
+int mdg_dgemm_grouped(const void *device_plan, int64_t num_tiles, int grid, void *stream);
+
 /*
  * The raw hipError_t of the last HIP call that failed inside this library on the
  * calling thread (0 if none): the detail behind an MDG_ERR_HIP return.

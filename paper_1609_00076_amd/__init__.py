@@ -5,12 +5,17 @@ dimensions, exported by libmdg.so through the C ABI in include/mdg.h. This
 package is the thin Python binding (ctypes); torch supplies device memory and
 streams only.
 """
-from .binding import (MdgError, dgemm, load, mdg_dgemm, mdg_dgemm_ex, mdg_dgemm_split,
-                      mdg_dgemm_split_workspace_size, mdg_last_hip_error, mdg_num_variants,
-                      mdg_select_variant, mdg_split_max_slices, mdg_split_slices,
-                      mdg_status_string, mdg_variant_info, mdg_variant_name, mdg_version)
+from .binding import (MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, load, mdg_dgemm,
+                      mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_split,
+                      mdg_dgemm_split_workspace_size, mdg_gemm_desc, mdg_grouped_plan,
+                      mdg_grouped_plan_bytes, mdg_grouped_tile_classes, mdg_last_hip_error,
+                      mdg_num_variants, mdg_select_variant, mdg_split_max_slices,
+                      mdg_split_slices, mdg_status_string, mdg_variant_info, mdg_variant_name,
+                      mdg_version)
 
-__all__ = ["MdgError", "dgemm", "load", "mdg_dgemm", "mdg_dgemm_ex", "mdg_dgemm_split",
-           "mdg_dgemm_split_workspace_size", "mdg_last_hip_error", "mdg_num_variants",
+__all__ = ["MDG_SCHEDULE_LPT", "MDG_SCHEDULE_NATURAL", "MdgError", "dgemm", "load", "mdg_dgemm",
+           "mdg_dgemm_ex", "mdg_dgemm_grouped", "mdg_dgemm_split", "mdg_dgemm_split_workspace_size",
+           "mdg_gemm_desc", "mdg_grouped_plan", "mdg_grouped_plan_bytes",
+           "mdg_grouped_tile_classes", "mdg_last_hip_error", "mdg_num_variants",
            "mdg_select_variant", "mdg_split_max_slices", "mdg_split_slices", "mdg_status_string",
            "mdg_variant_info", "mdg_variant_name", "mdg_version"]

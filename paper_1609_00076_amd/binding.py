@@ -18,6 +18,18 @@ from .build import LIB_PATH
 
 _lib = None
 
+MDG_SCHEDULE_NATURAL = 0
+MDG_SCHEDULE_LPT = 1
+
+
+class mdg_gemm_desc(ctypes.Structure):
+    """One GEMM of a grouped launch (the C struct of the same name)."""
+    _fields_ = [("transa", ctypes.c_char), ("transb", ctypes.c_char),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("alpha", ctypes.c_double), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("beta", ctypes.c_double), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
 
 class MdgError(RuntimeError):
     def __init__(self, status: int):
@@ -82,6 +94,17 @@ def load():
     lib.mdg_dgemm_split.restype = ci
     lib.mdg_split_slices.argtypes = [ci, ch, i64, i64, vp, i64, ci, vp, vp, vp]
     lib.mdg_split_slices.restype = ci
+    dptr = ctypes.POINTER(mdg_gemm_desc)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.mdg_grouped_tile_classes.argtypes = []
+    lib.mdg_grouped_tile_classes.restype = ci
+    lib.mdg_grouped_plan_bytes.argtypes = [ci, dptr, i32p]
+    lib.mdg_grouped_plan_bytes.restype = i64
+    lib.mdg_grouped_plan.argtypes = [ci, dptr, i32p, ci, vp, i64, ctypes.POINTER(i64),
+                                     ctypes.POINTER(ci)]
+    lib.mdg_grouped_plan.restype = ci
+    lib.mdg_dgemm_grouped.argtypes = [vp, i64, ci, vp]
+    lib.mdg_dgemm_grouped.restype = ci
     _lib = lib
     return lib
 
@@ -241,6 +264,54 @@ def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents,
     ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
     return load().mdg_split_slices(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),
                                    int(nslices), sp, ep, _stream(stream))
+
+
+def mdg_grouped_tile_classes() -> int:
+    return load().mdg_grouped_tile_classes()
+
+
+def _descs_array(descs):
+    arr = (mdg_gemm_desc * max(1, len(descs)))()
+    for i, d in enumerate(descs):
+        arr[i] = d
+    return arr
+
+
+def _classes_array(tile_class, count):
+    if tile_class is None:
+        return None
+    arr = (ctypes.c_int32 * max(1, count))(*[int(c) for c in tile_class])
+    return arr
+
+
+def mdg_grouped_plan_bytes(descs, tile_class=None) -> int:
+    """descs: sequence of mdg_gemm_desc; tile_class: per-GEMM classes or None (automatic)."""
+    return load().mdg_grouped_plan_bytes(len(descs), _descs_array(descs),
+                                         _classes_array(tile_class, len(descs)))
+
+
+def mdg_grouped_plan(descs, tile_class, schedule, plan):
+    """Write the plan into `plan` (a writable host buffer, e.g. a numpy uint8 array).
+
+    Returns (status, num_tiles, bad_index).
+    """
+    import numpy as np
+    buf = np.ascontiguousarray(plan)
+    if buf is not plan or buf.dtype != np.uint8:
+        raise TypeError("plan must be a contiguous numpy uint8 array")
+    nt = ctypes.c_int64(0)
+    bad = ctypes.c_int(-1)
+    st = load().mdg_grouped_plan(len(descs), _descs_array(descs),
+                                 _classes_array(tile_class, len(descs)), int(schedule),
+                                 buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes,
+                                 ctypes.byref(nt), ctypes.byref(bad))
+    return st, nt.value, bad.value
+
+
+def mdg_dgemm_grouped(device_plan, num_tiles, grid=0, stream=None) -> int:
+    """Launch a plan held in device memory (tensor or address)."""
+    dp = _raw_ptr(device_plan, 64, "device_plan")
+    return load().mdg_dgemm_grouped(dp, int(num_tiles), int(grid), _stream(stream))
 
 
 def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=None, variant=-1):

@@ -15,7 +15,9 @@
 // outside C are masked, so the padding rows of every operand are never read or written.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <vector>
 #include <cstdint>
 #include <cstring>
 
@@ -177,12 +179,21 @@ __device__ __forceinline__ void store_panel(const PanelMap<PER_THREAD>& mp, doub
 // C(i0 + l%16, j0 + l/16 + 4r): lanes 0..15 of each accumulator register cover 16 consecutive
 // rows of one column of C, which makes the epilogue's loads and stores of column-major C
 // contiguous 128-byte runs.
+// LDS doubles one tile of configuration C with transposes TA, TB needs (two buffers per operand).
 template <class C, bool TA, bool TB>
-__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::MIN_WAVES_PER_EU)))
-dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+constexpr int tile_lds_doubles() {
+  return 2 * C::KT * (LdsLayout<C, TA, TB>::A + LdsLayout<C, TA, TB>::B);
+}
+
+// The whole computation of tile (tm, tn) of C by one workgroup; `smem` holds
+// tile_lds_doubles<C, TA, TB>() doubles. Shared by the single-GEMM kernels and the grouped one,
+// so a GEMM computed in a grouped launch is bitwise the one computed alone with the same tile.
+// Ends with a workgroup barrier, so the caller may reuse `smem` right away.
+template <class C, bool TA, bool TB>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, double* smem) {
   using L = LdsLayout<C, TA, TB>;
-  __shared__ double As[2][C::KT * L::A];
-  __shared__ double Bs[2][C::KT * L::B];
+  double (*As)[C::KT * L::A] = reinterpret_cast<double (*)[C::KT * L::A]>(smem);
+  double (*Bs)[C::KT * L::B] = reinterpret_cast<double (*)[C::KT * L::B]>(smem + 2 * C::KT * L::A);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -191,8 +202,6 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   const int wave_n = wave / C::WAVES_M;
   const int l16 = lane & 15, lq = lane >> 4;
 
-  int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
   const int64_t row0 = (int64_t)tm * C::MT;
   const int64_t col0 = (int64_t)tn * C::NT;
 
@@ -239,7 +248,8 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
     for (int bj = 0; bj < C::BN; ++bj) acc[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
 
   double ra[C::A_PER_THREAD], rb[C::B_PER_THREAD];
-  const int num_k = (int)((g.k + C::KT - 1) / C::KT);
+  // alpha == 0 or k == 0: no product (A and B are not read); the epilogue forms beta*C.
+  const int num_k = (g.alpha == 0.0) ? 0 : (int)((g.k + C::KT - 1) / C::KT);
   const int k_left_last = (int)(g.k - (int64_t)(num_k - 1) * C::KT);  // 1..KT
 
   auto fetch = [&](int kt) {
@@ -252,9 +262,11 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
     }
   };
 
-  fetch(0);
-  store_panel(ma, As[0], ra);
-  store_panel(mb, Bs[0], rb);
+  if (num_k > 0) {
+    fetch(0);
+    store_panel(ma, As[0], ra);
+    store_panel(mb, Bs[0], rb);
+  }
   __syncthreads();
 
   const int a_frag = lq * L::A + wave_m * C::WM + l16;  // this lane's A fragment at k-step 0
@@ -311,6 +323,16 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
       }
     }
   }
+  __syncthreads();
+}
+
+template <class C, bool TA, bool TB>
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(C::MIN_WAVES_PER_EU)))
+dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  __shared__ double smem[tile_lds_doubles<C, TA, TB>()];
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  gemm_tile<C, TA, TB>(g, tm, tn, smem);
 }
 
 // C := beta*C over the logical m x n matrix (beta == 0 writes zeros without reading C). This is
@@ -341,6 +363,7 @@ using Mid8 = Cfg<128, 64, 16, 32, 32, 6, 0>;     // 8 waves, each 32x32
 using Big16p = Cfg<128, 128, 16, 32, 32, 8, 1>;  // Big16 with read-friendly LDS padding
 using Small16 = Cfg<64, 64, 16, 16, 16, 8, 1>;   // 16 waves, each 16x16 (one MFMA chain)
 using Skinny = Cfg<64, 64, 16, 32, 32, 4, 1, true>;  // 4 waves of 32x32, old C loaded up front
+using Tiny = Cfg<32, 32, 16, 16, 16, 8, 0>;     // 4 waves, each 16x16 (one MFMA chain)
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -393,8 +416,85 @@ const Variant kVariants[] = {
     make_variant<Big16p>("mfma_f64_128x128x16_w32x32_pad", 860),
     make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 630),
     make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
+    make_variant<Tiny>("mfma_f64_32x32x16_w16x16", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// ------------------------------------------------------------------------------------------------
+// Grouped launch: many independent GEMMs in one persistent kernel.
+//
+// A plan (built on the host, copied to the device by the caller) holds one descriptor per GEMM and
+// a list of tiles (gemm, tm, tn) in schedule order. Workgroup w processes list entries
+// w, w + G, w + 2G, ... (G = grid size) and computes each with the same tile code the single-GEMM
+// kernels use: tile class 0 is the 64x64 tile of variant "mfma_f64_64x64x16_w32x32", class 1 the
+// 32x32 tile of "mfma_f64_32x32x16_w16x16". Nothing is allocated or cleared at launch time, so a
+// launch can be captured in a graph and replayed.
+// ------------------------------------------------------------------------------------------------
+using GroupedCfg0 = Small;
+using GroupedCfg1 = Tiny;
+constexpr int kGroupedClasses = 2;
+constexpr int kGroupedThreads = 256;
+static_assert(GroupedCfg0::THREADS == kGroupedThreads && GroupedCfg1::THREADS == kGroupedThreads,
+              "grouped tile classes share one workgroup size");
+constexpr int kPlanMagic = 0x4D444750;  // "MDGP"
+
+struct GroupedDesc {
+  GemmArgs g;
+  int32_t ta, tb, tile_class, tiles_m;
+  int32_t tiles_n, pad0, pad1, pad2;
+};
+
+struct PlanHeader {
+  int32_t magic, version, count, pad;
+  int64_t num_tiles;
+  int64_t desc_offset, tile_offset;  // bytes from the plan start
+  int64_t pad2[3];
+};
+static_assert(sizeof(PlanHeader) == 64, "plan header layout");
+
+constexpr int ilog_max(int a, int b) { return a > b ? a : b; }
+constexpr int kGroupedLds = ilog_max(
+    ilog_max(ilog_max(tile_lds_doubles<GroupedCfg0, false, false>(), tile_lds_doubles<GroupedCfg0, true, true>()),
+             ilog_max(tile_lds_doubles<GroupedCfg0, false, true>(), tile_lds_doubles<GroupedCfg0, true, false>())),
+    ilog_max(ilog_max(tile_lds_doubles<GroupedCfg1, false, false>(), tile_lds_doubles<GroupedCfg1, true, true>()),
+             ilog_max(tile_lds_doubles<GroupedCfg1, false, true>(), tile_lds_doubles<GroupedCfg1, true, false>())));
+
+template <class C>
+__device__ __forceinline__ void grouped_tile(const GroupedDesc& d, int tm, int tn, double* smem) {
+  if (d.ta) {
+    if (d.tb) gemm_tile<C, true, true>(d.g, tm, tn, smem);
+    else      gemm_tile<C, true, false>(d.g, tm, tn, smem);
+  } else {
+    if (d.tb) gemm_tile<C, false, true>(d.g, tm, tn, smem);
+    else      gemm_tile<C, false, false>(d.g, tm, tn, smem);
+  }
+}
+
+__global__ void __launch_bounds__(kGroupedThreads) __attribute__((amdgpu_waves_per_eu(4)))
+grouped_kernel(const int8_t* plan) {
+  __shared__ double smem[kGroupedLds];
+  const PlanHeader* h = reinterpret_cast<const PlanHeader*>(plan);
+  const GroupedDesc* descs = reinterpret_cast<const GroupedDesc*>(plan + h->desc_offset);
+  const int4* tiles = reinterpret_cast<const int4*>(plan + h->tile_offset);
+  const int64_t n = h->num_tiles;
+  for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+    const int4 e = tiles[t];
+    const GroupedDesc& d = descs[e.x];
+    if (d.tile_class == 0) grouped_tile<GroupedCfg0>(d, e.y, e.z, smem);
+    else                   grouped_tile<GroupedCfg1>(d, e.y, e.z, smem);
+  }
+}
+
+struct GroupedTileRef {
+  double cost;
+  int32_t gemm, tm, tn;
+};
+
+int grouped_tile_dims(int cls, int* mt, int* nt) {
+  if (cls == 0) { *mt = GroupedCfg0::MT; *nt = GroupedCfg0::NT; return 0; }
+  if (cls == 1) { *mt = GroupedCfg1::MT; *nt = GroupedCfg1::NT; return 0; }
+  return -1;
+}
 
 bool is_notrans(char t) { return t == 'N' || t == 'n'; }
 bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
@@ -587,6 +687,119 @@ int mdg_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double 
               int64_t ldc, void* stream) {
   return mdg_dgemm_ex(MDG_VARIANT_AUTO, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
                       ldc, stream);
+}
+
+
+// ---- grouped launch -----------------------------------------------------------------------------
+
+// Tiles a GEMM contributes: none when nothing is computed (empty, or quick return).
+static int64_t grouped_tiles_of(const mdg_gemm_desc& d, int cls) {
+  if (d.m <= 0 || d.n <= 0) return 0;
+  if ((d.alpha == 0.0 || d.k == 0) && d.beta == 1.0) return 0;
+  int mt, nt;
+  if (grouped_tile_dims(cls, &mt, &nt)) return 0;
+  return ceil_div(d.m, mt) * ceil_div(d.n, nt);
+}
+
+static int grouped_class_of(const mdg_gemm_desc& d, const int32_t* tile_class, int i) {
+  if (tile_class) return tile_class[i];
+  return (d.m < 48 || d.n < 48) ? 1 : 0;
+}
+
+int mdg_grouped_tile_classes(void) { return kGroupedClasses; }
+
+int64_t mdg_grouped_plan_bytes(int count, const mdg_gemm_desc* descs, const int32_t* tile_class) {
+  if (count < 0 || (count > 0 && descs == nullptr)) return -1;
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    const int cls = grouped_class_of(descs[i], tile_class, i);
+    if (cls < 0 || cls >= kGroupedClasses) return -1;
+    tiles += grouped_tiles_of(descs[i], cls);
+  }
+  return (int64_t)sizeof(PlanHeader) + (int64_t)count * (int64_t)sizeof(GroupedDesc) + tiles * 16;
+}
+
+int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_class,
+                     int schedule, void* plan, int64_t plan_bytes, int64_t* num_tiles,
+                     int* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (count < 0 || (count > 0 && descs == nullptr)) return 1;
+  if (schedule != MDG_SCHEDULE_NATURAL && schedule != MDG_SCHEDULE_LPT) return 4;
+  const int64_t need = mdg_grouped_plan_bytes(count, descs, tile_class);
+  if (need < 0) return 3;
+  if (plan == nullptr || plan_bytes < need) return 5;
+  std::vector<GroupedTileRef> refs;
+  int8_t* base = static_cast<int8_t*>(plan);
+  PlanHeader* h = reinterpret_cast<PlanHeader*>(base);
+  GroupedDesc* gd = reinterpret_cast<GroupedDesc*>(base + sizeof(PlanHeader));
+  for (int i = 0; i < count; ++i) {
+    const mdg_gemm_desc& d = descs[i];
+    const int info = check_args(d.transa, d.transb, d.m, d.n, d.k, d.alpha, d.A, d.lda, d.B, d.ldb,
+                                d.beta, d.C, d.ldc);
+    if (info) {
+      if (bad_index) *bad_index = i;
+      return 100 + info;
+    }
+    const int cls = grouped_class_of(d, tile_class, i);
+    int mt = 0, nt = 0;
+    grouped_tile_dims(cls, &mt, &nt);
+    const bool ta = is_trans(d.transa), tb = is_trans(d.transb);
+    const int64_t rows_a = ta ? d.k : d.m, cols_a = ta ? d.m : d.k;
+    const int64_t rows_b = tb ? d.n : d.k, cols_b = tb ? d.k : d.n;
+    GroupedDesc& o = gd[i];
+    std::memset(&o, 0, sizeof(o));
+    o.g = GemmArgs{d.m, d.n, d.k, d.lda, d.ldb, d.ldc, d.alpha, d.beta, d.A, d.B, d.C,
+                   cols_a > 0 ? (cols_a - 1) * d.lda + rows_a : 0,
+                   cols_b > 0 ? (cols_b - 1) * d.ldb + rows_b : 0};
+    o.ta = ta;
+    o.tb = tb;
+    o.tile_class = cls;
+    const int64_t ntiles = grouped_tiles_of(d, cls);
+    o.tiles_m = ntiles ? (int32_t)ceil_div(d.m, mt) : 0;
+    o.tiles_n = ntiles ? (int32_t)ceil_div(d.n, nt) : 0;
+    if (ntiles && (o.tiles_m > INT32_MAX / 2 || o.tiles_n > INT32_MAX / 2)) {
+      if (bad_index) *bad_index = i;
+      return MDG_ERR_SIZE;
+    }
+    const double cost = (double)mt * nt * (double)(d.alpha == 0.0 ? 1 : (d.k > 0 ? d.k : 1));
+    for (int32_t tn = 0; tn < o.tiles_n; ++tn)
+      for (int32_t tm = 0; tm < o.tiles_m; ++tm) refs.push_back(GroupedTileRef{cost, i, tm, tn});
+  }
+  if (schedule == MDG_SCHEDULE_LPT)
+    std::stable_sort(refs.begin(), refs.end(),
+                     [](const GroupedTileRef& a, const GroupedTileRef& b) { return a.cost > b.cost; });
+  h->magic = kPlanMagic;
+  h->version = 1;
+  h->count = count;
+  h->pad = 0;
+  h->num_tiles = (int64_t)refs.size();
+  h->desc_offset = (int64_t)sizeof(PlanHeader);
+  h->tile_offset = (int64_t)sizeof(PlanHeader) + (int64_t)count * (int64_t)sizeof(GroupedDesc);
+  h->pad2[0] = h->pad2[1] = h->pad2[2] = 0;
+  int32_t* tl = reinterpret_cast<int32_t*>(base + h->tile_offset);
+  for (size_t t = 0; t < refs.size(); ++t) {
+    tl[4 * t + 0] = refs[t].gemm;
+    tl[4 * t + 1] = refs[t].tm;
+    tl[4 * t + 2] = refs[t].tn;
+    tl[4 * t + 3] = 0;
+  }
+  if (num_tiles) *num_tiles = (int64_t)refs.size();
+  return MDG_SUCCESS;
+}
+
+int mdg_dgemm_grouped(const void* device_plan, int64_t num_tiles, int grid, void* stream) {
+  if (device_plan == nullptr) return 1;
+  if (num_tiles < 0) return 2;
+  if (grid < 0) return 3;
+  if ((reinterpret_cast<uintptr_t>(device_plan) & 15) != 0) return 1;
+  if (num_tiles == 0) return MDG_SUCCESS;
+  const int dc = device_check();
+  if (dc) return dc;
+  int64_t g = grid > 0 ? grid : (int64_t)kCUs * 4;
+  if (g > num_tiles) g = num_tiles;
+  const int8_t* p = static_cast<const int8_t*>(device_plan);
+  return launch(reinterpret_cast<const void*>(&grouped_kernel), dim3((unsigned)g),
+                dim3(kGroupedThreads), static_cast<hipStream_t>(stream), p);
 }
 
 }  // extern "C"

@@ -1,0 +1,92 @@
+"""Autotuner for grouped dgemm launches: measured search over tile classes, schedules and grids.
+
+A policy is (threshold, schedule, grid): GEMM i uses the 32x32 tile (class 1) when
+min(m_i, n_i) < threshold and the 64x64 tile (class 0) otherwise; the tile list is in natural or
+largest-first (LPT) order; `grid` persistent workgroups walk it. Each candidate is timed as a
+captured graph of one grouped launch, replayed; the fastest is kept. Results are stored in a JSON
+database keyed by device architecture, HIP version and a workload signature, and read back by
+`best_policy`.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import binding as b
+from .grouped import GroupedPlan
+
+DB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_db.json")
+THRESHOLDS = (0, 40, 64, 96, 160, 1 << 30)
+SCHEDULES = (b.MDG_SCHEDULE_NATURAL, b.MDG_SCHEDULE_LPT)
+GRIDS = (256, 512, 1024, 2048)
+DEFAULT_POLICY = {"threshold": 48, "schedule": b.MDG_SCHEDULE_LPT, "grid": 1024}
+
+
+def classes_for(gemms, threshold):
+    return [1 if min(g["m"], g["n"]) < threshold else 0 for g in gemms]
+
+
+def device_key(signature: str) -> str:
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", props.name).split(":")[0]
+    return f"{arch}|hip{torch.version.hip}|{signature}"
+
+
+def time_policy(gemms, policy, reps=10, warmup=3):
+    """Milliseconds per replay of a graph holding one grouped launch under `policy`."""
+    import torch
+    plan = GroupedPlan(gemms, classes_for(gemms, policy["threshold"]), policy["schedule"])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            plan.launch(policy["grid"])
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.launch(policy["grid"])
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_grouped(gemms, signature, thresholds=THRESHOLDS, schedules=SCHEDULES, grids=GRIDS,
+                 reps=10, db_path=DB_PATH, log=None):
+    """Time every candidate policy on `gemms`, store the best under `signature`, return it."""
+    results = []
+    for th in thresholds:
+        for sc in schedules:
+            for gr in grids:
+                pol = {"threshold": th, "schedule": sc, "grid": gr}
+                ms = time_policy(gemms, pol, reps=reps)
+                results.append({**pol, "ms": round(ms, 5)})
+                if log:
+                    log(f"[tune] {pol} {ms:.4f} ms")
+    best = min(results, key=lambda r: r["ms"])
+    entry = {"policy": {k: best[k] for k in ("threshold", "schedule", "grid")},
+             "ms": best["ms"], "candidates": results}
+    db = load_db(db_path)
+    db[device_key(signature)] = entry
+    with open(db_path, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    return entry
+
+
+def load_db(db_path=DB_PATH):
+    if os.path.exists(db_path):
+        with open(db_path) as f:
+            return json.load(f)
+    return {}
+
+
+def best_policy(signature, db_path=DB_PATH):
+    """The stored policy for this device and signature, else the default one."""
+    entry = load_db(db_path).get(device_key(signature))
+    return dict(entry["policy"]) if entry else dict(DEFAULT_POLICY)

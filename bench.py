@@ -337,6 +337,38 @@ def grouped_workload(args, torch, mdg):
     print(json.dumps(out), flush=True)
 
 
+def served_workload(args, torch, mdg):
+    """Poisson stream of dgemm requests through the continuous-batching server."""
+    from paper_1609_00076_amd import serve
+    reqs = serve.make_stream(args.rate, args.duration, seed=synth_seed(5), lo=32, hi=4096,
+                             split_fraction=0.2, phi=8)
+    log(f"[bench] serving {len(reqs)} requests over {args.duration} s")
+    warm = serve.make_stream(200, 0.5, seed=synth_seed(5) + 1, lo=32, hi=512)
+    srv = serve.Server(budget_bytes=args.budget_gb << 30)
+    srv.run(warm)  # compile-free warm-up of allocator and streams
+    stats = srv.run(reqs)
+    s = stats.summary()
+    log(f"[bench] served: {s}")
+    out = {
+        "metric": METRIC + " (served-stream leg)",
+        "value": s["aggregate_tflops"], "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * s["wall_s"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic: operands filled on the device from per-request seeds",
+        "config": {"workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, m,n,k "
+                               "log-uniform in [32,4096], transposes iid, 80% native, 20% split "
+                               f"(phi=8, {serve.SPLIT_SLICES[8]} slices), HBM budget "
+                               f"{args.budget_gb} GB"},
+        "served": s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def synth_seed(workload):
+    import synth
+    return synth.seed_for(workload, 0, 0)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,11 +380,14 @@ def main():
     ap.add_argument("--trans", default="", help="comma list of NN,NT,TN,TT (default: all four)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force one kernel variant for every GEMM (default -1: the library's choice)")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "split", "grouped"],
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "split", "grouped", "served"],
                     help="sweep: the native dgemm sweep (default, the headline line); split: the "
                          "split-precision INT8 path against the native kernel")
     ap.add_argument("--split-size", type=int, default=8192)
     ap.add_argument("--tune", action="store_true", help="grouped: run the autotuner first")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=int, default=64, help="served: HBM budget in GiB")
     ap.add_argument("--tune-db", default="", help="grouped: tuning database path")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times (the "
@@ -388,6 +423,9 @@ def main():
         return
     if args.workload == "grouped":
         grouped_workload(args, torch, mdg)
+        return
+    if args.workload == "served":
+        served_workload(args, torch, mdg)
         return
 
     shapes_filter = None

@@ -115,9 +115,11 @@ const char *mdg_status_string(int status);
  * v_mfma_i32_16x16x64_i8, and the sum is recombined, unscaled and combined with alpha, beta and
  * the old C in binary64. The result approximates the FP64 product: the error is about
  * k * 2^(-7*nslices) times the product of the row and column maxima, so entries whose magnitudes
- * spread widely within a row or column need more slices (at exponent spread phi, nslices = 7 for
- * phi = 0, 8 for phi = 8, 10 for phi = 32 give max |C - Cref| / (|A||B|)_ij below 1e-13 on the
- * tested shapes). Inputs must be finite: NaN or Inf in A or B gives an unspecified result.
+ * spread widely within a row or column need more slices. Measured for entries u * 2^e, e uniform in
+ * [-phi, phi]: at k = 8192, nslices = 7 (phi = 0), 8 (phi = 8), 10 (phi = 32) keep
+ * max |C - Cref| / (|A||B|)_ij below 1e-13; at k as small as 32, phi = 8 needs 9, and phi = 32 is
+ * not reached even with 12 (a short row spanning 2^64 leaves (|A||B|)_ij far below the product of
+ * the maxima). Inputs must be finite: NaN or Inf in A or B gives an unspecified result.
  * ------------------------------------------------------------------------------------------ */
 
 /* Largest supported `nslices` (the smallest is 1). */

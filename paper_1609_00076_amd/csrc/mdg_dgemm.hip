@@ -28,6 +28,8 @@
 // in this namespace is private to the library all the same (only the extern "C" API is exported).
 namespace mdg_impl {
 
+constexpr int kCUs = 256;  // MI355X compute units
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kVersion = 100;  // 0.1.0
@@ -349,6 +351,278 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
 }
 
 // ------------------------------------------------------------------------------------------------
+// Ring kernels: the k-panels of op(A) and op(B) stream from memory straight into a ring of STAGES
+// LDS stages (buffer loads with an LDS destination, no register staging), STAGES - 1 panels ahead
+// of the arithmetic, and the MFMAs of each panel's last k-substeps are issued after the barrier
+// that ends the panel, where they cover the LDS latency of the next panel's first fragments.
+//
+// A direct load moves 16 bytes per lane into LDS at (wave-uniform base) + 16 * lane, so a wave
+// fills one 1 KB chunk per load. Each 16 bytes are two neighbours along the operand's stored
+// (contiguous) dimension, which fixes two LDS layouts:
+//   k-major (operand contiguous along m or n): a chunk is 128 consecutive rows of one k-row; k-rows
+//     are R + 8 doubles apart, so that the fragment reads of k-rows two apart use disjoint halves
+//     of the 64 LDS banks;
+//   row-major (operand contiguous along k): each row holds the panel's 16 k-values as 8 pairs of
+//     16 bytes, pair p of row i stored in slot p ^ f(i), f(i) = (i & 7) ^ ((i >> 3) & 1), which makes
+//     16-byte fragment reads of 8 (32 banks) or 16 (64 banks) consecutive rows conflict-free.
+// A fragment read of a k-pair serves two MFMAs, so the MFMA k-index of lane group c (lanes
+// 16c..16c+15) in substep e of pair h is 8h + 2c + e; both operands use this order, which only
+// permutes the terms of each panel's sum.
+// ------------------------------------------------------------------------------------------------
+template <int MT_, int NT_, int WM_, int WN_, int STAGES_, int MIN_WAVES_PER_EU_>
+struct RingCfg {
+  static constexpr int MT = MT_, NT = NT_, KT = 16, WM = WM_, WN = WN_, STAGES = STAGES_;
+  static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;
+  static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
+  static constexpr int WAVES = WAVES_M * WAVES_N;
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int BM = WM / 16, BN = WN / 16;
+  static constexpr int PAIRS = KT / 8;  // k-pairs of MFMA substeps per panel
+  static constexpr int ROW_A = MT + 8, ROW_B = NT + 8;  // k-major row strides (doubles)
+  static constexpr int STAGE_A = KT * ROW_A, STAGE_B = KT * ROW_B;
+  static constexpr int STAGE = STAGE_A + STAGE_B;
+  static constexpr int LDS_DOUBLES = STAGES * STAGE;
+  static constexpr int A_LOADS = MT * KT / 128 / WAVES, B_LOADS = NT * KT / 128 / WAVES;
+  static constexpr int LOADS = A_LOADS + B_LOADS;  // direct loads per wave per panel
+  static_assert(MT % 128 == 0 && NT % 128 == 0, "k-major chunks are 128-row pieces of a k-row");
+  static_assert((MT * KT / 128) % WAVES == 0 && (NT * KT / 128) % WAVES == 0, "chunk split");
+  static_assert(MT % WM == 0 && NT % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave grid");
+  static_assert(STAGES >= 2 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
+  static_assert(THREADS <= 1024, "workgroup size");
+};
+
+__device__ __forceinline__ int ring_swz(int row) { return (row & 7) ^ ((row >> 3) & 1); }
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+// Compiler-level ordering of LDS accesses around a bare s_barrier (which by itself does not keep
+// the compiler from moving memory operations across it).
+__device__ __forceinline__ void ring_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// s_waitcnt with vmcnt(N) and lgkmcnt(0), expcnt untouched (gfx9 encoding).
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N <= 63, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+template <int LOADS, int MAXN>
+__device__ __forceinline__ void wait_panels(int newer) {  // newer = panels allowed in flight
+  if constexpr (MAXN >= 3) { if (newer >= 3) { wait_vm_lgkm0<3 * LOADS>(); return; } }
+  if constexpr (MAXN >= 2) { if (newer == 2) { wait_vm_lgkm0<2 * LOADS>(); return; } }
+  if constexpr (MAXN >= 1) { if (newer == 1) { wait_vm_lgkm0<1 * LOADS>(); return; } }
+  wait_vm_lgkm0<0>();
+}
+
+// Per-lane global byte offset (from the panel origin) and wave-uniform LDS chunk base (doubles,
+// within the operand's part of a stage) of direct load u of one operand with R panel rows.
+template <class R, int ROWS, int ROW, bool CONTIG_K>
+__device__ __forceinline__ void ring_map(int wave, int lane, int u, int64_t ld, uint32_t& off,
+                                         int& lds) {
+  const int c = wave + R::WAVES * u;
+  if (!CONTIG_K) {
+    constexpr int per_row = ROWS / 128;
+    const int q = c / per_row, part = c % per_row;
+    const int i = part * 128 + 2 * lane;
+    off = (uint32_t)((i + (int64_t)q * ld) * 8);
+    lds = q * ROW + part * 128;
+  } else {
+    const int i = c * 8 + (lane >> 3);
+    const int p = (lane & 7) ^ ring_swz(i);
+    off = (uint32_t)((2 * p + (int64_t)i * ld) * 8);
+    lds = c * 128;
+  }
+}
+
+// Zero the entries with k-index >= k_left of one stage (ragged last panel).
+template <class R, bool TA, bool TB>
+__device__ __forceinline__ void ring_mask_tail(double* st, int k_left) {
+  double* As = st;
+  double* Bs = st + R::STAGE_A;
+  for (int e = threadIdx.x; e < R::MT * R::KT; e += R::THREADS) {
+    if (!TA) { const int q = e / R::MT, i = e % R::MT; if (q >= k_left) As[q * R::ROW_A + i] = 0.0; }
+    else { const int i = e / R::KT, q = e % R::KT;
+           if (q >= k_left) As[i * R::KT + 2 * ((q >> 1) ^ ring_swz(i)) + (q & 1)] = 0.0; }
+  }
+  for (int e = threadIdx.x; e < R::NT * R::KT; e += R::THREADS) {
+    if (TB) { const int q = e / R::NT, j = e % R::NT; if (q >= k_left) Bs[q * R::ROW_B + j] = 0.0; }
+    else { const int j = e / R::KT, q = e % R::KT;
+           if (q >= k_left) Bs[j * R::KT + 2 * ((q >> 1) ^ ring_swz(j)) + (q & 1)] = 0.0; }
+  }
+}
+
+// Tile (tm, tn) of C by one workgroup of a ring configuration; `smem` holds R::LDS_DOUBLES.
+template <class R, bool TA, bool TB>
+__device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, double* smem) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave_m = wave % R::WAVES_M, wave_n = wave / R::WAVES_M;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int64_t row0 = (int64_t)tm * R::MT, col0 = (int64_t)tn * R::NT;
+
+  // Direct-load placement (k-major for an operand contiguous along m or n).
+  uint32_t a_off[R::A_LOADS], b_off[R::B_LOADS];
+  int a_lds[R::A_LOADS], b_lds[R::B_LOADS];
+#pragma unroll
+  for (int u = 0; u < R::A_LOADS; ++u)
+    ring_map<R, R::MT, R::ROW_A, TA>(wave, lane, u, g.lda, a_off[u], a_lds[u]);
+#pragma unroll
+  for (int u = 0; u < R::B_LOADS; ++u)
+    ring_map<R, R::NT, R::ROW_B, !TB>(wave, lane, u, g.ldb, b_off[u], b_lds[u]);
+
+  const int64_t a_org = TA ? row0 * g.lda : row0;
+  const int64_t a_step = TA ? (int64_t)R::KT : (int64_t)R::KT * g.lda;
+  const int64_t b_org = TB ? col0 : col0 * g.ldb;
+  const int64_t b_step = TB ? (int64_t)R::KT * g.ldb : (int64_t)R::KT;
+
+  const int num_k = (g.alpha == 0.0) ? 0 : (int)((g.k + R::KT - 1) / R::KT);
+  const int k_left_last = (int)(g.k - (int64_t)(num_k - 1) * R::KT);  // 1..KT
+
+  auto issue = [&](int p) {
+    double* st = smem + (p % R::STAGES) * R::STAGE;
+    const int64_t ao = a_org + p * a_step, bo = b_org + p * b_step;
+    const rsrc_t ra = make_rsrc(g.A + ao, g.ext_a - ao);
+    const rsrc_t rb = make_rsrc(g.B + bo, g.ext_b - bo);
+#pragma unroll
+    for (int u = 0; u < R::A_LOADS; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void_ptr)(st + a_lds[u]), 16, a_off[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < R::B_LOADS; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void_ptr)(st + R::STAGE_A + b_lds[u]), 16,
+                                               b_off[u], 0, 0, 0);
+  };
+
+  // Fragment addresses (doubles from the stage base) of this lane for pair 0; pair h adds h * 8
+  // k-rows (k-major) or flips slot bit 2 (row-major: slot (4h + c) ^ f = (4h) ^ (c ^ f)).
+  const int ai = wave_m * R::WM + l16, bj = wave_n * R::WN + l16;
+  const int a_kmaj = 2 * lq * R::ROW_A + ai;
+  const int b_kmaj = R::STAGE_A + 2 * lq * R::ROW_B + bj;
+  const int a_rmaj = ai * R::KT + 2 * (lq ^ ring_swz(l16));
+  const int b_rmaj = R::STAGE_A + bj * R::KT + 2 * (lq ^ ring_swz(l16));
+
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  auto read_frags = [&](const double* st, int h, d2 (&fa)[R::BM], d2 (&fb)[R::BN]) {
+#pragma unroll
+    for (int b = 0; b < R::BM; ++b) {
+      if (!TA) {
+        const double* p = st + a_kmaj + 8 * h * R::ROW_A + 16 * b;
+        fa[b] = (d2){p[0], p[R::ROW_A]};
+      } else {
+        fa[b] = *reinterpret_cast<const d2*>(st + ((a_rmaj + 16 * b * R::KT) ^ (8 * h)));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < R::BN; ++b) {
+      if (TB) {
+        const double* p = st + b_kmaj + 8 * h * R::ROW_B + 16 * b;
+        fb[b] = (d2){p[0], p[R::ROW_B]};
+      } else {
+        fb[b] = *reinterpret_cast<const d2*>(st + ((b_rmaj + 16 * b * R::KT) ^ (8 * h)));
+      }
+    }
+  };
+
+  d4 acc[R::BM][R::BN];
+#pragma unroll
+  for (int i = 0; i < R::BM; ++i)
+#pragma unroll
+    for (int j = 0; j < R::BN; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  auto mfma_pair = [&](const d2 (&fa)[R::BM], const d2 (&fb)[R::BN]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int i = 0; i < R::BM; ++i)
+#pragma unroll
+        for (int j = 0; j < R::BN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[j][e], fa[i][e], acc[i][j], 0, 0, 0);
+  };
+
+  if (num_k > 0) {
+    const int pre = num_k < R::STAGES - 1 ? num_k : R::STAGES - 1;
+    for (int p = 0; p < pre; ++p) issue(p);
+    wait_panels<R::LOADS, R::STAGES - 2>(pre - 1);
+    ring_barrier();
+    if (num_k == 1 && k_left_last < R::KT) {
+      ring_mask_tail<R, TA, TB>(smem, k_left_last);
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      ring_barrier();
+    }
+    d2 fa0[R::BM], fb0[R::BN], fa1[R::BM], fb1[R::BN];
+    read_frags(smem, 0, fa0, fb0);
+    // Every panel but the last: its pair 1 is multiplied after the barrier that ends it. (The last
+    // panel is peeled off so that the loop body has one path through it.)
+    for (int t = 0; t < num_k - 1; ++t) {
+      const double* st = smem + (t % R::STAGES) * R::STAGE;
+      if (t + R::STAGES - 1 < num_k) issue(t + R::STAGES - 1);
+      read_frags(st, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);  // keep these reads ahead of the MFMAs below
+      mfma_pair(fa0, fb0);
+      const int last_loaded = (t + R::STAGES - 1 < num_k) ? t + R::STAGES - 1 : num_k - 1;
+      wait_panels<R::LOADS, R::STAGES - 2>(last_loaded - (t + 1));
+      ring_barrier();
+      const double* nst = smem + ((t + 1) % R::STAGES) * R::STAGE;
+      if (t + 1 == num_k - 1 && k_left_last < R::KT) {
+        ring_mask_tail<R, TA, TB>(const_cast<double*>(nst), k_left_last);
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        ring_barrier();
+      }
+      read_frags(nst, 0, fa0, fb0);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pair(fa1, fb1);
+    }
+    read_frags(smem + ((num_k - 1) % R::STAGES) * R::STAGE, 1, fa1, fb1);
+    mfma_pair(fa0, fb0);
+    mfma_pair(fa1, fb1);
+  }
+
+  // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
+  const int64_t i0 = row0 + ai, j0 = col0 + wave_n * R::WN + lq;
+  double* const cbase = g.C + j0 * g.ldc + i0;
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int bj2 = 0; bj2 < R::BN; ++bj2) {
+    double cb[R::BM][4];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t dj = 16 * bj2 + 4 * r;
+        const bool col_ok = j0 + dj < g.n;
+#pragma unroll
+        for (int bi = 0; bi < R::BM; ++bi)
+          cb[bi][r] = (col_ok && i0 + 16 * bi < g.m) ? cbase[dj * g.ldc + 16 * bi] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t dj = 16 * bj2 + 4 * r;
+      if (j0 + dj >= g.n) continue;
+#pragma unroll
+      for (int bi = 0; bi < R::BM; ++bi) {
+        if (i0 + 16 * bi < g.m) {
+          const double v = alpha * acc[bi][bj2][r];
+          cbase[dj * g.ldc + 16 * bi] = (beta != 0.0) ? v + beta * cb[bi][r] : v;
+        }
+      }
+    }
+  }
+}
+
+template <class R, bool TA, bool TB>
+__global__ void __launch_bounds__(R::THREADS) __attribute__((amdgpu_waves_per_eu(R::MIN_WAVES_PER_EU)))
+dgemm_ring_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  __shared__ __attribute__((aligned(16))) double smem[R::LDS_DOUBLES];
+  int tm, tn;
+  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  ring_tile<R, TA, TB>(g, tm, tn, smem);
+}
+
+// ------------------------------------------------------------------------------------------------
 // Variant table.
 // ------------------------------------------------------------------------------------------------
 using Big = Cfg<128, 128, 16, 64, 64, 2, 0>;     // 4 waves, each 64x64 (16 MFMA chains)
@@ -364,10 +638,13 @@ using Big16p = Cfg<128, 128, 16, 32, 32, 8, 1>;  // Big16 with read-friendly LDS
 using Small16 = Cfg<64, 64, 16, 16, 16, 8, 1>;   // 16 waves, each 16x16 (one MFMA chain)
 using Skinny = Cfg<64, 64, 16, 32, 32, 4, 1, true>;  // 4 waves of 32x32, old C loaded up front
 using Tiny = Cfg<32, 32, 16, 16, 16, 8, 0>;     // 4 waves, each 16x16 (one MFMA chain)
+using Ring256 = RingCfg<256, 128, 64, 32, 3, 4>;    // 16 waves of 64x32, 3 stages, 1 WG per CU
+using Ring256w = RingCfg<256, 128, 64, 64, 3, 2>;   // 8 waves of 64x64, 3 stages
+using Ring128x4 = RingCfg<128, 128, 32, 32, 4, 4>;  // 16 waves of 32x32, 4 stages
+using Ring128w = RingCfg<128, 256, 32, 64, 3, 4>;   // 16 waves of 32x64, 3 stages
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
-constexpr int kCUs = 256;             // MI355X compute units
 constexpr int kLdsPerCU = 160 * 1024;  // bytes of LDS per CU on gfx950
 
 struct Variant {
@@ -386,6 +663,16 @@ constexpr int resident_wgs() {
   constexpr int by_lds = kLdsPerCU / lds;
   constexpr int by_waves = (C::MIN_WAVES_PER_EU * 4) / C::WAVES;
   return by_lds < by_waves ? by_lds : by_waves;
+}
+
+template <class R>
+constexpr Variant make_ring_variant(const char* name, int eff_permil) {
+  constexpr int by_lds = kLdsPerCU / (R::LDS_DOUBLES * 8);
+  constexpr int by_waves = (R::MIN_WAVES_PER_EU * 4) / R::WAVES;
+  constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
+  return Variant{name, R::MT, R::NT, R::KT, R::THREADS, wgs > 0 ? wgs : 1, eff_permil,
+                 {{dgemm_ring_kernel<R, false, false>, dgemm_ring_kernel<R, false, true>},
+                  {dgemm_ring_kernel<R, true, false>, dgemm_ring_kernel<R, true, true>}}};
 }
 
 template <class C>
@@ -417,6 +704,10 @@ const Variant kVariants[] = {
     make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 630),
     make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
     make_variant<Tiny>("mfma_f64_32x32x16_w16x16", 0),
+    make_ring_variant<Ring256>("ring_f64_256x128x16_w64x32_s3", 901),
+    make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 889),
+    make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 846),
+    make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 896),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -501,6 +792,14 @@ bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 int64_t max1(int64_t x) { return x > 1 ? x : 1; }
 
 // Argument checks in dgemm argument order; 0 or the 1-based position of the first bad argument.
+// Every kernel addresses the elements of one k-panel by 32-bit byte offsets from the panel origin;
+// a panel spans at most max(mt, nt) leading dimensions (plus less than one), so this bound keeps
+// every offset below 4 GiB.
+bool panel_offsets_fit(int64_t tile_rows, int64_t lda, int64_t ldb) {
+  const int64_t ld = lda > ldb ? lda : ldb;
+  return (tile_rows + 1) * ld < ((int64_t)1 << 29);
+}
+
 int check_args(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                const double* C, int64_t ldc) {
@@ -632,7 +931,7 @@ const char* mdg_status_string(int status) {
     case MDG_ERR_HIP: return "HIP runtime error";
     case MDG_ERR_VARIANT: return "unknown kernel variant";
     case MDG_ERR_DEVICE: return "current device is not gfx950";
-    case MDG_ERR_SIZE: return "m and n too large for one launch";
+    case MDG_ERR_SIZE: return "problem too large for one launch (grid size or leading dimension)";
     default: return "unknown status";
   }
 }
@@ -673,6 +972,7 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
   const int64_t tiles = tiles_m * tiles_n;
   if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;  // beyond one launch's grid
+  if (!panel_offsets_fit(v.mt > v.nt ? v.mt : v.nt, lda, ldb)) return MDG_ERR_SIZE;
   const int64_t rows_a = is_trans(transa) ? k : m, cols_a = is_trans(transa) ? m : k;
   const int64_t rows_b = is_trans(transb) ? n : k, cols_b = is_trans(transb) ? k : n;
   GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C,
@@ -757,7 +1057,8 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_
     const int64_t ntiles = grouped_tiles_of(d, cls);
     o.tiles_m = ntiles ? (int32_t)ceil_div(d.m, mt) : 0;
     o.tiles_n = ntiles ? (int32_t)ceil_div(d.n, nt) : 0;
-    if (ntiles && (o.tiles_m > INT32_MAX / 2 || o.tiles_n > INT32_MAX / 2)) {
+    if (ntiles && (o.tiles_m > INT32_MAX / 2 || o.tiles_n > INT32_MAX / 2 ||
+                   !panel_offsets_fit(mt > nt ? mt : nt, d.lda, d.ldb))) {
       if (bad_index) *bad_index = i;
       return MDG_ERR_SIZE;
     }

@@ -369,9 +369,13 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
 // 16c..16c+15) in substep e of pair h is 8h + 2c + e; both operands use this order, which only
 // permutes the terms of each panel's sum.
 // ------------------------------------------------------------------------------------------------
-template <int MT_, int NT_, int WM_, int WN_, int STAGES_, int MIN_WAVES_PER_EU_>
+template <int MT_, int NT_, int WM_, int WN_, int STAGES_, int MIN_WAVES_PER_EU_, int SCHED_ = 0>
 struct RingCfg {
   static constexpr int MT = MT_, NT = NT_, KT = 16, WM = WM_, WN = WN_, STAGES = STAGES_;
+  // Instruction order inside a k-step. 0: each panel's fragment reads strictly before the MFMAs
+  // they overlap; 1: MFMAs interleaved one by one with the direct loads and fragment reads, so
+  // that the matrix pipe restarts at once after a barrier and LDS traffic is spread out.
+  static constexpr int SCHED = SCHED_;
   static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
   static constexpr int WAVES = WAVES_M * WAVES_N;
@@ -387,7 +391,7 @@ struct RingCfg {
   static_assert(MT % 128 == 0 && NT % 128 == 0, "k-major chunks are 128-row pieces of a k-row");
   static_assert((MT * KT / 128) % WAVES == 0 && (NT * KT / 128) % WAVES == 0, "chunk split");
   static_assert(MT % WM == 0 && NT % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave grid");
-  static_assert(STAGES >= 2 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
+  static_assert(STAGES >= 2 && STAGES <= 4 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
   static_assert(THREADS <= 1024, "workgroup size");
 };
 
@@ -416,6 +420,27 @@ __device__ __forceinline__ void wait_panels(int newer) {  // newer = panels allo
   if constexpr (MAXN >= 2) { if (newer == 2) { wait_vm_lgkm0<2 * LOADS>(); return; } }
   if constexpr (MAXN >= 1) { if (newer == 1) { wait_vm_lgkm0<1 * LOADS>(); return; } }
   wait_vm_lgkm0<0>();
+}
+
+// Scheduling-group patterns (sched_group_barrier masks: 0x008 MFMA, 0x020 VMEM read,
+// 0x100 DS read): N times one MFMA followed by one instruction of class MASK.
+template <int MASK, int N>
+__device__ __forceinline__ void sched_mfma_then() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(MASK, 1, 0);
+    sched_mfma_then<MASK, N - 1>();
+  }
+}
+
+// N times: M MFMAs followed by one instruction of class MASK.
+template <int M, int MASK, int N>
+__device__ __forceinline__ void sched_mfmas_then() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, M, 0);
+    __builtin_amdgcn_sched_group_barrier(MASK, 1, 0);
+    sched_mfmas_then<M, MASK, N - 1>();
+  }
 }
 
 // Per-lane global byte offset (from the panel origin) and wave-uniform LDS chunk base (doubles,
@@ -544,9 +569,11 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
   };
 
   if (num_k > 0) {
-    const int pre = num_k < R::STAGES - 1 ? num_k : R::STAGES - 1;
+    // Panels 0 .. STAGES-1 fill the ring; panel p + STAGES goes into p's slot right after the
+    // barrier that ends panel p, so loads run about STAGES - 1 panels ahead of their use.
+    const int pre = num_k < R::STAGES ? num_k : R::STAGES;
     for (int p = 0; p < pre; ++p) issue(p);
-    wait_panels<R::LOADS, R::STAGES - 2>(pre - 1);
+    wait_panels<R::LOADS, R::STAGES - 1>(pre - 1);
     ring_barrier();
     if (num_k == 1 && k_left_last < R::KT) {
       ring_mask_tail<R, TA, TB>(smem, k_left_last);
@@ -555,17 +582,40 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     }
     d2 fa0[R::BM], fb0[R::BN], fa1[R::BM], fb1[R::BN];
     read_frags(smem, 0, fa0, fb0);
-    // Every panel but the last: its pair 1 is multiplied after the barrier that ends it. (The last
-    // panel is peeled off so that the loop body has one path through it.)
-    for (int t = 0; t < num_k - 1; ++t) {
+    // Fragment reads per read_frags: one per block (16-byte row-major reads, or two 8-byte k-major
+    // reads the compiler pairs up).
+    constexpr int kReads = R::BM + R::BN;
+    int t = 0;
+    // Steady state: every iteration issues a full panel of loads and the panel read after its
+    // barrier is not the last one (which may need its k-tail masked), so the body has a single
+    // path. Pair 1 of panel t is multiplied after the barrier that ends the panel.
+    for (; t + R::STAGES < num_k && t + 2 < num_k; ++t) {
       const double* st = smem + (t % R::STAGES) * R::STAGE;
-      if (t + R::STAGES - 1 < num_k) issue(t + R::STAGES - 1);
       read_frags(st, 1, fa1, fb1);
-      __builtin_amdgcn_sched_barrier(0);  // keep these reads ahead of the MFMAs below
+      if (R::SCHED == 0) __builtin_amdgcn_sched_barrier(0);  // reads ahead of the MFMAs below
       mfma_pair(fa0, fb0);
-      const int last_loaded = (t + R::STAGES - 1 < num_k) ? t + R::STAGES - 1 : num_k - 1;
-      wait_panels<R::LOADS, R::STAGES - 2>(last_loaded - (t + 1));
+      if (R::SCHED == 1) sched_mfma_then<0x100, kReads>();
+      wait_vm_lgkm0<(R::STAGES - 2) * R::LOADS>();
       ring_barrier();
+      issue(t + R::STAGES);
+      read_frags(smem + ((t + 1) % R::STAGES) * R::STAGE, 0, fa0, fb0);
+      if (R::SCHED == 0) __builtin_amdgcn_sched_barrier(0);
+      mfma_pair(fa1, fb1);
+      if (R::SCHED == 1) {
+        sched_mfma_then<0x100, kReads>();
+        sched_mfmas_then<2, 0x020, R::LOADS>();
+      }
+    }
+    // Drain: the last panels are loaded or in flight; the last one may need its k-tail masked.
+    for (; t < num_k - 1; ++t) {
+      const double* st = smem + (t % R::STAGES) * R::STAGE;
+      read_frags(st, 1, fa1, fb1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_pair(fa0, fb0);
+      const int last_issued = (t + R::STAGES - 1 < num_k) ? t + R::STAGES - 1 : num_k - 1;
+      wait_panels<R::LOADS, R::STAGES - 2>(last_issued - (t + 1));
+      ring_barrier();
+      if (t + R::STAGES < num_k) issue(t + R::STAGES);
       const double* nst = smem + ((t + 1) % R::STAGES) * R::STAGE;
       if (t + 1 == num_k - 1 && k_left_last < R::KT) {
         ring_mask_tail<R, TA, TB>(const_cast<double*>(nst), k_left_last);
@@ -642,6 +692,9 @@ using Ring256 = RingCfg<256, 128, 64, 32, 3, 4>;    // 16 waves of 64x32, 3 stag
 using Ring256w = RingCfg<256, 128, 64, 64, 3, 2>;   // 8 waves of 64x64, 3 stages
 using Ring128x4 = RingCfg<128, 128, 32, 32, 4, 4>;  // 16 waves of 32x32, 4 stages
 using Ring128w = RingCfg<128, 256, 32, 64, 3, 4>;   // 16 waves of 32x64, 3 stages
+using Ring256i = RingCfg<256, 128, 64, 32, 3, 4, 1>;    // Ring256, interleaved issue
+using Ring128x4i = RingCfg<128, 128, 32, 32, 4, 4, 1>;  // Ring128x4, interleaved issue
+using Ring128wi = RingCfg<128, 256, 32, 64, 3, 4, 1>;   // Ring128w, interleaved issue
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -704,10 +757,13 @@ const Variant kVariants[] = {
     make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 630),
     make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
     make_variant<Tiny>("mfma_f64_32x32x16_w16x16", 0),
-    make_ring_variant<Ring256>("ring_f64_256x128x16_w64x32_s3", 901),
-    make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 889),
-    make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 846),
-    make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 896),
+    make_ring_variant<Ring256>("ring_f64_256x128x16_w64x32_s3", 893),
+    make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 0),
+    make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
+    make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
+    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", 924),
+    make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
+    make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

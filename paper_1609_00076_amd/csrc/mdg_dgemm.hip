@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <vector>
 #include <cstdint>
@@ -695,6 +696,7 @@ using Ring128w = RingCfg<128, 256, 32, 64, 3, 4>;   // 16 waves of 32x64, 3 stag
 using Ring256i = RingCfg<256, 128, 64, 32, 3, 4, 1>;    // Ring256, interleaved issue
 using Ring128x4i = RingCfg<128, 128, 32, 32, 4, 4, 1>;  // Ring128x4, interleaved issue
 using Ring128wi = RingCfg<128, 256, 32, 64, 3, 4, 1>;   // Ring128w, interleaved issue
+using Ring256wi = RingCfg<256, 128, 64, 64, 3, 2, 1>;   // 8 waves of 64x64, interleaved issue
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -704,8 +706,9 @@ struct Variant {
   const char* name;
   int mt, nt, kt, threads;
   int wgs_per_cu;   // workgroups resident per CU (LDS- and register-limited)
-  int eff_permil;   // measured share of the FP64 MFMA peak on large square shapes, per mille;
-                    // 0 keeps the variant out of the automatic choice
+  int eff_permil[2][2];  // [transa][transb]: measured share of the FP64 MFMA peak on large
+                         // square shapes, per mille; 0 keeps the variant out of the automatic
+                         // choice
   KernelFn fn[2][2];  // [transa][transb]
 };
 
@@ -718,25 +721,32 @@ constexpr int resident_wgs() {
   return by_lds < by_waves ? by_lds : by_waves;
 }
 
+struct Eff {
+  int nn, nt, tn, tt;
+  constexpr Eff(int all) : nn(all), nt(all), tn(all), tt(all) {}
+  constexpr Eff(int nn_, int nt_, int tn_, int tt_) : nn(nn_), nt(nt_), tn(tn_), tt(tt_) {}
+};
+
 template <class R>
-constexpr Variant make_ring_variant(const char* name, int eff_permil) {
+constexpr Variant make_ring_variant(const char* name, Eff e) {
   constexpr int by_lds = kLdsPerCU / (R::LDS_DOUBLES * 8);
   constexpr int by_waves = (R::MIN_WAVES_PER_EU * 4) / R::WAVES;
   constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
-  return Variant{name, R::MT, R::NT, R::KT, R::THREADS, wgs > 0 ? wgs : 1, eff_permil,
+  return Variant{name, R::MT, R::NT, R::KT, R::THREADS, wgs > 0 ? wgs : 1,
+                 {{e.nn, e.nt}, {e.tn, e.tt}},
                  {{dgemm_ring_kernel<R, false, false>, dgemm_ring_kernel<R, false, true>},
                   {dgemm_ring_kernel<R, true, false>, dgemm_ring_kernel<R, true, true>}}};
 }
 
 template <class C>
-constexpr Variant make_variant(const char* name, int eff_permil) {
+constexpr Variant make_variant(const char* name, Eff e) {
   return Variant{name,
                  C::MT,
                  C::NT,
                  C::KT,
                  C::THREADS,
                  resident_wgs<C>() > 0 ? resident_wgs<C>() : 1,
-                 eff_permil,
+                 {{e.nn, e.nt}, {e.tn, e.tt}},
                  {{dgemm_mfma_kernel<C, false, false>, dgemm_mfma_kernel<C, false, true>},
                   {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
 }
@@ -754,16 +764,17 @@ const Variant kVariants[] = {
     make_variant<Tall16>("mfma_f64_256x128x16_w64x32", 847),
     make_variant<Mid8>("mfma_f64_128x64x16_w32x32", 790),
     make_variant<Big16p>("mfma_f64_128x128x16_w32x32_pad", 860),
-    make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 630),
+    make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 0),
     make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
     make_variant<Tiny>("mfma_f64_32x32x16_w16x16", 0),
     make_ring_variant<Ring256>("ring_f64_256x128x16_w64x32_s3", 893),
     make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 0),
     make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
     make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
-    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", 924),
+    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(925, 925, 918, 918)),
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
+    make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(905, 905, 930, 930)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -880,20 +891,29 @@ int check_args(char transa, char transb, int64_t m, int64_t n, int64_t k, double
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Shape-driven choice. A launch runs in rounds of kCUs * wgs_per_cu workgroups; a round costs
-// about wgs_per_cu * mt * nt * k / efficiency whether or not every slot is filled (a partly filled
-// round is latency-bound, not faster per tile). The variant with the smallest estimate wins; ties
-// go to the earlier entry.
-int pick_variant(int64_t m, int64_t n, int64_t /*k*/) {
+// Shape-driven choice. Tiles are dealt over the kCUs CUs, so a CU processes about
+// ceil(tiles / kCUs) tiles, up to wgs_per_cu of them at a time. Its time is estimated as
+//   tiles per CU * mt * nt * (k + overhead) / (efficiency * occupancy),
+// where efficiency is the measured one for the transpose case, occupancy = (resident / wgs_per_cu)^(1/3)
+// discounts a CU holding fewer workgroups than it could (less latency hiding), and the overhead of
+// kTileOverheadK / resident k-steps stands for a tile's prologue and epilogue (old C read, C
+// written), which co-resident workgroups partly overlap. The smallest estimate wins; ties go to
+// the earlier entry.
+constexpr double kTileOverheadK = 128.0;
+
+int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
   int best = 0;
   double best_cost = 0.0;
   for (int v = 0; v < kNumVariants; ++v) {
     const Variant& var = kVariants[v];
-    if (var.eff_permil <= 0) continue;
+    const int eff = var.eff_permil[ta][tb];
+    if (eff <= 0) continue;
     const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
-    const int64_t slots = (int64_t)kCUs * var.wgs_per_cu;
-    const double rounds = (double)ceil_div(tiles, slots);
-    const double cost = rounds * var.wgs_per_cu * var.mt * var.nt / (var.eff_permil * 1e-3);
+    const int64_t per_cu = ceil_div(tiles, kCUs);
+    const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
+    const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
+    const double cost = (double)per_cu * var.mt * var.nt * ((double)k + kTileOverheadK / resident) /
+                        (eff * 1e-3 * occupancy);
     if (best_cost == 0.0 || cost < best_cost) {
       best = v;
       best_cost = cost;
@@ -998,7 +1018,7 @@ int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k
   if (!(is_notrans(transa) || is_trans(transa)) || !(is_notrans(transb) || is_trans(transb)))
     return -1;
   if (m <= 0 || n <= 0 || k <= 0 || alpha == 0.0) return -1;
-  return pick_variant(m, n, k);
+  return pick_variant(is_trans(transa), is_trans(transb), m, n, k);
 }
 
 int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
@@ -1023,7 +1043,9 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
                   s, m, n, beta, C, ldc);
   }
 
-  const int vid = (variant == MDG_VARIANT_AUTO) ? pick_variant(m, n, k) : variant;
+  const int vid = (variant == MDG_VARIANT_AUTO)
+                      ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
+                      : variant;
   const Variant& v = kVariants[vid];
   const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
   const int64_t tiles = tiles_m * tiles_n;

@@ -129,9 +129,9 @@ int mdg_split_max_slices(void);
 
 /*
  * Bytes of device workspace mdg_dgemm_split needs for these sizes, or -1 for invalid sizes or
- * slice count. Layout: int8 slices of op(A) [nslices][m][kp], of op(B)^T [nslices][n][kp]
- * (kp = k rounded up to a multiple of 64, zero padded), then int32 exponents of the m rows and
- * n columns, each part aligned to 256 bytes.
+ * slice count. Layout: the int8 slices of op(A) (rows = m) and of op(B)^T (rows = n), each in
+ * the k-panel tiles described at mdg_split_slices, then int32 exponents of the m rows and n
+ * columns, each part aligned to 256 bytes.
  */
 int64_t mdg_dgemm_split_workspace_size(int64_t m, int64_t n, int64_t k, int nslices);
 
@@ -152,8 +152,11 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
 /*
  * The slicing step alone, for one operand: operand 0 slices the rows of op(A) (rows = m, trans =
  * transa, X = A, ld = lda), operand 1 the columns of op(B) (rows = n, trans = transb, X = B,
- * ld = ldb). Writes slices[s*rows*kp + r*kp + p] (kp = k rounded up to 64; zero for p >= k) and
- * exponents[r] = e with max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row). Returns 0, or
+ * ld = ldb). With rp = rows and kp = k, each rounded up to a multiple of 64, writes slice s of
+ * entry (r, p) at slices[s*rp*kp + (p/64)*rp*64 + r*64 + p%64] for r < rp, p < kp (zero for
+ * r >= rows or p >= k: one 64-row block of one slice for one 64-deep k-step is 4 KiB of
+ * contiguous bytes), so `slices` holds nslices*rp*kp bytes; and exponents[r] = e with
+ * max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row). Returns 0, or
  * 1 operand, 2 trans, 3 rows < 0, 4 k < 0, 5 X NULL, 6 ld too small, 7 nslices out of range,
  * 8 output NULL, or a negative runtime code.
  */

@@ -260,7 +260,8 @@ def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents,
         if rows > 0 and k > 0 and ld >= max(1, k if row_contig else rows) else 0
     ok_s = 1 <= int(nslices) <= mdg_split_max_slices()
     xp = _ptr(X, need_x, "X")
-    sp = _raw_ptr(slices, int(nslices) * int(rows) * kp if ok_s and rows > 0 else 0, "slices")
+    rp = (int(rows) + 63) // 64 * 64
+    sp = _raw_ptr(slices, int(nslices) * rp * kp if ok_s and rows > 0 else 0, "slices")
     ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
     return load().mdg_split_slices(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),
                                    int(nslices), sp, ep, _stream(stream))

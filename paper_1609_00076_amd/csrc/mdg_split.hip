@@ -15,6 +15,8 @@
 // op(B), padded with zeros to a multiple of 64 in k.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cstdint>
 
 #include "mdg.h"
@@ -39,9 +41,17 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, int64_t bytes) {
 
 // ------------------------------------------------------------------------------------------------
 // Slicing. X is a rows x k matrix given by its storage: x(r,p) = X[r*ld + p] when ROW_CONTIG
-// (op(A) with transa = T, op(B)^T with transb = N), else X[p*ld + r]. Output: exps[r] and
-// out[s*rows*kp + r*kp + p] for p < kp (zero for p >= k).
+// (op(A) with transa = T, op(B)^T with transb = N), else X[p*ld + r]. Output: exps[r] and the
+// slices in k-panel tiles: byte (s, r, p) at slice_offset(s, r, p) for r < rp (rows rounded up
+// to 64) and p < kp (k rounded up to 64), zero for r >= rows or p >= k. One 64-row block of one
+// slice for one 64-deep k-step is thus 4 KiB of contiguous bytes.
 // ------------------------------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int64_t round64(int64_t x) { return (x + 63) / 64 * 64; }
+
+__device__ __forceinline__ int64_t slice_offset(int s, int64_t r, int64_t p, int64_t rp,
+                                                int64_t kp) {
+  return (int64_t)s * rp * kp + (p >> 6) * rp * 64 + r * 64 + (p & 63);
+}
 __device__ __forceinline__ int row_exponent(double mx) {
   int e = 0;
   if (mx != 0.0) (void)frexp(mx, &e);  // mx = f * 2^e, f in [0.5, 1)
@@ -72,7 +82,15 @@ __global__ void __launch_bounds__(256) slice_rows_kernel(const double* X, int64_
                                                          int32_t* exps) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= rows) return;
+  const int64_t rp = round64(rows);
+  if (r >= rp) return;
+  if (r >= rows) {  // padding row of the last 64-row block
+    for (int64_t p0 = (int64_t)lane * 16; p0 < kp; p0 += 64 * 16)
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = (v4i){0, 0, 0, 0};
+    return;
+  }
   const double* x = X + r * ld;
   double mx = 0.0;
   for (int64_t p = lane; p < k; p += 64) mx = fmax(mx, fabs(x[p]));
@@ -91,7 +109,7 @@ __global__ void __launch_bounds__(256) slice_rows_kernel(const double* X, int64_
     slice16<S>(v, q);
 #pragma unroll
     for (int s = 0; s < S; ++s)
-      *reinterpret_cast<v4i*>(out + (int64_t)s * rows * kp + r * kp + p0) = q[s];
+      *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = q[s];
   }
 }
 
@@ -116,7 +134,15 @@ __global__ void __launch_bounds__(256) slice_cols_kernel(const double* X, int64_
     red[rr][16] = m2;
   }
   __syncthreads();
-  if (!live) return;
+  const int64_t rp = round64(rows);
+  if (!live) {
+    if (r < rp)  // padding row of the last 64-row block
+      for (int64_t p0 = (int64_t)ph * 16; p0 < kp; p0 += 16 * 16)
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = (v4i){0, 0, 0, 0};
+    return;
+  }
   const int e = row_exponent(red[rr][16]);
   if (ph == 0) exps[r] = e;
   for (int64_t p0 = (int64_t)ph * 16; p0 < kp; p0 += 16 * 16) {
@@ -130,7 +156,7 @@ __global__ void __launch_bounds__(256) slice_cols_kernel(const double* X, int64_
     slice16<S>(v, q);
 #pragma unroll
     for (int s = 0; s < S; ++s)
-      *reinterpret_cast<v4i*>(out + (int64_t)s * rows * kp + r * kp + p0) = q[s];
+      *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = q[s];
   }
 }
 
@@ -151,8 +177,8 @@ struct SplitArgs {
   double alpha, beta;
   double* C;
   int64_t ldc;
-  const int8_t* As;  // [S][m][kp]
-  const int8_t* Bs;  // [S][n][kp]
+  const int8_t* As;  // slices of op(A) in k-panel tiles (see slice_offset), rows rounded to 64
+  const int8_t* Bs;  // slices of op(B)^T, the same way
   const int32_t* ea;
   const int32_t* eb;
   int flush_steps;   // k-steps of 64 after which the INT32 accumulators are folded into FP64
@@ -200,20 +226,27 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
 
   // Global -> LDS staging: threads 0..255 carry A, 256..511 carry B; thread loads row
   // (tid % 256) >> 2, chunk tid & 3 of every slice of its operand.
-  const int ld_op = tid >> 8, ld_row = (tid & 255) >> 2, ld_chunk = tid & 3;
-  const int64_t slice_stride = ld_op ? g.n * g.kp : g.m * g.kp;
+  // ld_op is uniform within a wave; saying so keeps the buffer descriptor in scalar registers.
+  const int ld_op = __builtin_amdgcn_readfirstlane(tid >> 8);
+  const int ld_row = (tid & 255) >> 2, ld_chunk = tid & 3;
+  // Each operand's slices are k-panel tiles: this thread's 16 bytes of k-step ks of slice s are at
+  // s * slice_stride + ks * step_stride + off0, and a wave's 64 loads cover 1 KiB of contiguous
+  // bytes (16 rows of one 4 KiB tile).
+  const int64_t rp = round64(ld_op ? g.n : g.m);
+  const int64_t slice_stride = rp * g.kp, step_stride = rp * kKStep;
   const rsrc_t rsrc = make_rsrc(ld_op ? (const void*)g.Bs : (const void*)g.As, (int64_t)S * slice_stride);
-  const int64_t off0 = ((ld_op ? col0 : row0) + ld_row) * g.kp + ld_chunk * 16;
+  const int64_t off0 = ((ld_op ? col0 : row0) + ld_row) * kKStep + ld_chunk * 16;
   const int st_off = swz(ld_row, ld_chunk);
 
   // Two register sets of staged data: the panel for step ks+2 is loaded while step ks computes,
   // so a load has two k-steps of arithmetic to arrive before it is written to LDS.
   v4i pre0[S], pre1[S];
-  auto fetch = [&](v4i (&pre)[S], int64_t k0) {
+  auto fetch = [&](v4i (&pre)[S], int64_t ks) {
 #pragma unroll
     for (int s = 0; s < S; ++s)
-      // Offsets stay below 2^32: the host keeps S * m * kp and S * n * kp under 4 GiB.
-      pre[s] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(s * slice_stride + off0 + k0), 0, 0);
+      // Offsets stay below 2^32: the host keeps each operand's slice array under 4 GiB.
+      pre[s] = __builtin_amdgcn_raw_buffer_load_b128(
+          rsrc, (int)(s * slice_stride + ks * step_stride + off0), 0, 0);
   };
   auto stage = [&](const v4i (&pre)[S], int buf) {
 #pragma unroll
@@ -243,7 +276,7 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   const int nsteps = (int)(g.kp / kKStep);
   fetch(pre0, 0);
   stage(pre0, 0);
-  if (nsteps > 1) fetch(pre1, kKStep);
+  if (nsteps > 1) fetch(pre1, 1);
   __syncthreads();
 
   const int a_row = wave_m * 32 + l16;  // fragment rows this lane feeds (plus 16*bi)
@@ -251,10 +284,12 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   int since_fold = 0;
 
   // One k-step: compute from LDS buffer ks & 1; `next` holds step ks+1 (staged at the end),
-  // `spare` receives step ks+2.
-  auto step = [&](int ks, v4i (&next)[S], v4i (&spare)[S]) {
+  // `spare` receives step ks+2. STEADY: both exist, so the step has no branch around its memory
+  // operations (which keeps the compiler's wait counts exact across the loop back edge).
+  auto step = [&](auto steady_tag, int ks, v4i (&next)[S], v4i (&spare)[S]) {
+    constexpr bool STEADY = decltype(steady_tag)::value;
     const int buf = ks & 1;
-    if (ks + 2 < nsteps) fetch(spare, (int64_t)(ks + 2) * kKStep);
+    if (STEADY || ks + 2 < nsteps) fetch(spare, (int64_t)(ks + 2));
 
     v4i bf[S];
 #pragma unroll
@@ -275,12 +310,19 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
       fold();
       since_fold = 0;
     }
-    if (ks + 1 < nsteps) stage(next, buf ^ 1);
+    if (STEADY || ks + 1 < nsteps) stage(next, buf ^ 1);
     __syncthreads();
   };
-  for (int ks = 0; ks < nsteps; ks += 2) {
-    step(ks, pre1, pre0);
-    if (ks + 1 < nsteps) step(ks + 1, pre0, pre1);
+  using steady_t = std::integral_constant<bool, true>;
+  using tail_t = std::integral_constant<bool, false>;
+  int ks = 0;
+  for (; ks + 3 < nsteps; ks += 2) {
+    step(steady_t{}, ks, pre1, pre0);
+    step(steady_t{}, ks + 1, pre0, pre1);
+  }
+  for (; ks < nsteps; ks += 2) {
+    step(tail_t{}, ks, pre1, pre0);
+    if (ks + 1 < nsteps) step(tail_t{}, ks + 1, pre0, pre1);
   }
   if (since_fold) fold();
 
@@ -344,8 +386,8 @@ struct Layout {
 Layout layout(int64_t m, int64_t n, int64_t k, int S) {
   Layout L;
   L.kp = kpad(k);
-  L.a_bytes = align256((int64_t)S * m * L.kp);
-  L.b_bytes = align256((int64_t)S * n * L.kp);
+  L.a_bytes = align256((int64_t)S * round64(m) * L.kp);
+  L.b_bytes = align256((int64_t)S * round64(n) * L.kp);
   L.ea_off = L.a_bytes + L.b_bytes;
   L.eb_off = L.ea_off + align256(4 * m);
   L.total = L.eb_off + align256(4 * n);
@@ -366,9 +408,9 @@ int launch_slices(const Fns& f, bool row_contig, const double* X, int64_t ld, in
   if (rows == 0) return MDG_SUCCESS;
   void* argv[] = {&X, &ld, &rows, &k, &kp, &out, &exps};
   if (row_contig)
-    return launch(reinterpret_cast<const void*>(f.rows), dim3((unsigned)((rows + 3) / 4)),
+    return launch(reinterpret_cast<const void*>(f.rows), dim3((unsigned)(round64(rows) / 4)),
                   dim3(256), s, argv);
-  return launch(reinterpret_cast<const void*>(f.cols), dim3((unsigned)((rows + 15) / 16)),
+  return launch(reinterpret_cast<const void*>(f.cols), dim3((unsigned)(round64(rows) / 16)),
                 dim3(256), s, argv);
 }
 

@@ -69,17 +69,20 @@ def test_slices_match_reference_bytewise(operand, trans, S):
     rows_view[:, 3] = 0.0   # zero entries
     X, ld = _storage_from_rows(rows_view, operand, trans)
     kp = (k + 63) // 64 * 64
+    rp = (rows + 63) // 64 * 64
     want_q, want_e = oz.split_rows(rows_view, S)
     dX = torch.from_numpy(X).cuda()
-    sl = torch.full((S * rows * kp,), 99, dtype=torch.int8, device="cuda")
+    sl = torch.full((S * rp * kp,), 99, dtype=torch.int8, device="cuda")
     ex = torch.full((rows,), -999, dtype=torch.int32, device="cuda")
     assert mdg.mdg_split_slices(operand, trans, rows, k, dX, ld, S, sl, ex) == 0
     torch.cuda.synchronize()
-    got = sl.cpu().numpy().reshape(S, rows, kp)
+    # k-panel tiles [s][p // 64][r][p % 64] -> [s][r][p]
+    got = sl.cpu().numpy().reshape(S, kp // 64, rp, 64).transpose(0, 2, 1, 3).reshape(S, rp, kp)
     assert np.array_equal(ex.cpu().numpy(), want_e.astype(np.int32))
     for s in range(S):
-        assert np.array_equal(got[s, :, :k], want_q[s]), f"slice {s + 1}"
-        assert not np.any(got[s, :, k:]), "k padding must be zero"
+        assert np.array_equal(got[s, :rows, :k], want_q[s]), f"slice {s + 1}"
+        assert not np.any(got[s, :rows, k:]), "k padding must be zero"
+        assert not np.any(got[s, rows:, :]), "row padding must be zero"
 
 
 SHAPES = [(1, 1, 1), (17, 33, 5), (64, 64, 64), (65, 63, 130), (130, 70, 200), (200, 129, 64)]

@@ -75,89 +75,99 @@ __device__ __forceinline__ void slice16(double (&v)[16], v4i (&q)[S]) {
   }
 }
 
-// Row-contiguous storage: one wave per row.
-template <int S>
-__global__ void __launch_bounds__(256) slice_rows_kernel(const double* X, int64_t ld, int64_t rows,
-                                                         int64_t k, int64_t kp, int8_t* out,
-                                                         int32_t* exps) {
-  const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t rp = round64(rows);
-  if (r >= rp) return;
-  if (r >= rows) {  // padding row of the last 64-row block
-    for (int64_t p0 = (int64_t)lane * 16; p0 < kp; p0 += 64 * 16)
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = (v4i){0, 0, 0, 0};
-    return;
-  }
-  const double* x = X + r * ld;
+// Exponents are gathered in two passes. Pass 1 (split_max_kernel) takes the maximum magnitude of
+// each row over a chunk of k and merges the chunks with an integer atomicMax on the encoded
+// exponent enc = e + kExpBias (frexp's exponent is monotonic in the magnitude; 0 = no non-zero
+// entry yet, so the array starts zeroed). Pass 2 (split_tile_kernel) decodes it. NaN entries are
+// skipped by the maximum, as fmax does.
+constexpr int kExpBias = 2048;  // above the magnitude of any binary64 exponent
+constexpr int kMaxChunk = 512;  // k per workgroup in pass 1
+
+__device__ __forceinline__ int decode_exponent(int enc) { return enc ? enc - kExpBias : 0; }
+
+__global__ void __launch_bounds__(256) zero_i32_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) decode_exponents_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = decode_exponent(p[i]);
+}
+
+// Pass 1 over a 64-row block and a kMaxChunk-deep chunk of k; one thread per row (of the 64),
+// four k-phases. ROW_CONTIG: x(r,p) = X[r*ld + p]; else X[p*ld + r] (64 lanes read 512
+// contiguous bytes of one column).
+template <bool ROW_CONTIG>
+__global__ void __launch_bounds__(256) split_max_kernel(const double* X, int64_t ld, int64_t rows,
+                                                        int64_t k, int32_t* enc) {
+  __shared__ double red[4][64];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * kMaxChunk;
+  const int64_t p1 = p0 + kMaxChunk < k ? p0 + kMaxChunk : k;
   double mx = 0.0;
-  for (int64_t p = lane; p < k; p += 64) mx = fmax(mx, fabs(x[p]));
+  if (!ROW_CONTIG) {
+    const int r = t & 63;
+    if (row0 + r < rows)
+      for (int64_t p = p0 + (t >> 6); p < p1; p += 4) mx = fmax(mx, fabs(X[p * ld + row0 + r]));
+    red[t >> 6][r] = mx;
+  } else {
+    // wave w takes rows w, w+4, ...; its lanes read 64 consecutive k of a row
+    const int lane = t & 63, w = t >> 6;
+    for (int rr = w; rr < 64; rr += 4) {
+      double m2 = 0.0;
+      if (row0 + rr < rows)
+        for (int64_t p = p0 + lane; p < p1; p += 64) m2 = fmax(m2, fabs(X[(row0 + rr) * ld + p]));
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  const int e = row_exponent(mx);
-  if (lane == 0) exps[r] = e;
-  for (int64_t p0 = (int64_t)lane * 16; p0 < kp; p0 += 64 * 16) {
-    double v[16];
-#pragma unroll
-    for (int e2 = 0; e2 < 16; ++e2) {
-      v[e2] = 0.0;
-      if (p0 + e2 < k) v[e2] = ldexp(x[p0 + e2], -e);
+      for (int off = 32; off > 0; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off, 64));
+      if (lane == 0) red[0][rr] = m2;
     }
-    v4i q[S];
-    slice16<S>(v, q);
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-      *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = q[s];
+    if (t < 64) { red[1][t] = 0.0; red[2][t] = 0.0; red[3][t] = 0.0; }
+  }
+  __syncthreads();
+  if (t < 64 && row0 + t < rows) {
+    const double m = fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]));
+    if (m != 0.0) atomicMax(enc + row0 + t, row_exponent(m) + kExpBias);
   }
 }
 
-// Column-contiguous storage: a workgroup takes 16 rows; thread (rr, ph) reads row rr at k-phase ph,
-// so 16 neighbouring threads read 128 contiguous bytes.
-template <int S>
-__global__ void __launch_bounds__(256) slice_cols_kernel(const double* X, int64_t ld, int64_t rows,
+// Pass 2: one 64 x 64 block (rows x k) per workgroup, staged through LDS so that the global reads
+// are 512-byte runs for either storage order; thread t then slices row t/4, k-values
+// 16*(t%4) .. +15 and writes S 16-byte groups, so each slice's 4 KiB tile is written whole.
+template <int S, bool ROW_CONTIG>
+__global__ void __launch_bounds__(256) split_tile_kernel(const double* X, int64_t ld, int64_t rows,
                                                          int64_t k, int64_t kp, int8_t* out,
-                                                         int32_t* exps) {
-  __shared__ double red[16][17];
-  const int rr = threadIdx.x & 15, ph = threadIdx.x >> 4;
-  const int64_t r = (int64_t)blockIdx.x * 16 + rr;
-  const bool live = r < rows;
-  double mx = 0.0;
-  if (live)
-    for (int64_t p = ph; p < k; p += 16) mx = fmax(mx, fabs(X[p * ld + r]));
-  red[rr][ph] = mx;
-  __syncthreads();
-  if (ph == 0) {
-    double m2 = 0.0;
-    for (int q = 0; q < 16; ++q) m2 = fmax(m2, red[rr][q]);
-    red[rr][16] = m2;
-  }
-  __syncthreads();
+                                                         const int32_t* enc) {
+  __shared__ double tile[64][65];  // [row][k], one double of padding per row
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * 64;
   const int64_t rp = round64(rows);
-  if (!live) {
-    if (r < rp)  // padding row of the last 64-row block
-      for (int64_t p0 = (int64_t)ph * 16; p0 < kp; p0 += 16 * 16)
+  if (!ROW_CONTIG) {
+    const int r = t & 63;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = (v4i){0, 0, 0, 0};
-    return;
-  }
-  const int e = row_exponent(red[rr][16]);
-  if (ph == 0) exps[r] = e;
-  for (int64_t p0 = (int64_t)ph * 16; p0 < kp; p0 += 16 * 16) {
-    double v[16];
-#pragma unroll
-    for (int e2 = 0; e2 < 16; ++e2) {
-      v[e2] = 0.0;
-      if (p0 + e2 < k) v[e2] = ldexp(X[(p0 + e2) * ld + r], -e);
+    for (int i = 0; i < 16; ++i) {
+      const int pp = (t >> 6) + 4 * i;
+      tile[r][pp] = (row0 + r < rows && p0 + pp < k) ? X[(p0 + pp) * ld + row0 + r] : 0.0;
     }
-    v4i q[S];
-    slice16<S>(v, q);
+  } else {
+    const int pp = t & 63;
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      *reinterpret_cast<v4i*>(out + slice_offset(s, r, p0, rp, kp)) = q[s];
+    for (int i = 0; i < 16; ++i) {
+      const int r = (t >> 6) + 4 * i;
+      tile[r][pp] = (row0 + r < rows && p0 + pp < k) ? X[(row0 + r) * ld + p0 + pp] : 0.0;
+    }
   }
+  __syncthreads();
+  const int r = t >> 2, q0 = 16 * (t & 3);
+  const int e = (row0 + r < rows) ? decode_exponent(enc[row0 + r]) : 0;
+  double v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = ldexp(tile[r][q0 + i], -e);
+  v4i q[S];
+  slice16<S>(v, q);
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    *reinterpret_cast<v4i*>(out + slice_offset(s, row0 + r, p0 + q0, rp, kp)) = q[s];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -179,7 +189,7 @@ struct SplitArgs {
   int64_t ldc;
   const int8_t* As;  // slices of op(A) in k-panel tiles (see slice_offset), rows rounded to 64
   const int8_t* Bs;  // slices of op(B)^T, the same way
-  const int32_t* ea;
+  const int32_t* ea;  // encoded exponents (see decode_exponent)
   const int32_t* eb;
   int flush_steps;   // k-steps of 64 after which the INT32 accumulators are folded into FP64
 };
@@ -332,25 +342,26 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   for (int bi = 0; bi < kRB; ++bi) {
     const int64_t i = row0 + wave_m * 32 + 16 * bi + l16;
     if (i >= g.m) continue;
-    const int ei = g.ea[i];
+    const int ei = decode_exponent(g.ea[i]);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t j = col0 + wave_n * 16 + 4 * lq + r;
       if (j >= g.n) continue;
       double* c = g.C + j * g.ldc + i;
-      const double v = alpha * ldexp(cf[bi][r], ei + g.eb[j]);
+      const double v = alpha * ldexp(cf[bi][r], ei + decode_exponent(g.eb[j]));
       *c = (beta != 0.0) ? v + beta * *c : v;
     }
   }
 }
 
-typedef void (*SliceFn)(const double*, int64_t, int64_t, int64_t, int64_t, int8_t*, int32_t*);
+typedef void (*SliceFn)(const double*, int64_t, int64_t, int64_t, int64_t, int8_t*,
+                        const int32_t*);
 typedef void (*GemmFn)(SplitArgs, int, int);
 
 template <int S>
 struct Entry {
-  static constexpr SliceFn rows = slice_rows_kernel<S>;
-  static constexpr SliceFn cols = slice_cols_kernel<S>;
+  static constexpr SliceFn rows = split_tile_kernel<S, true>;
+  static constexpr SliceFn cols = split_tile_kernel<S, false>;
   static constexpr GemmFn gemm = split_gemm_kernel<S>;
 };
 
@@ -403,15 +414,30 @@ int launch(const void* fn, dim3 grid, dim3 block, hipStream_t s, void** argv) {
   return MDG_SUCCESS;
 }
 
+// Slices and encoded exponents of one operand; `exps` must hold zeros on entry.
 int launch_slices(const Fns& f, bool row_contig, const double* X, int64_t ld, int64_t rows,
                   int64_t k, int64_t kp, int8_t* out, int32_t* exps, hipStream_t s) {
   if (rows == 0) return MDG_SUCCESS;
+  const unsigned row_blocks = (unsigned)(round64(rows) / 64);
+  if (k > 0) {
+    void* argv[] = {&X, &ld, &rows, &k, &exps};
+    const dim3 grid(row_blocks, (unsigned)((k + kMaxChunk - 1) / kMaxChunk));
+    const void* fn = row_contig ? reinterpret_cast<const void*>(&split_max_kernel<true>)
+                                : reinterpret_cast<const void*>(&split_max_kernel<false>);
+    const int st = launch(fn, grid, dim3(256), s, argv);
+    if (st) return st;
+  }
+  if (kp == 0) return MDG_SUCCESS;  // k = 0: no slices; every exponent stays 0
   void* argv[] = {&X, &ld, &rows, &k, &kp, &out, &exps};
-  if (row_contig)
-    return launch(reinterpret_cast<const void*>(f.rows), dim3((unsigned)(round64(rows) / 4)),
-                  dim3(256), s, argv);
-  return launch(reinterpret_cast<const void*>(f.cols), dim3((unsigned)(round64(rows) / 16)),
-                dim3(256), s, argv);
+  return launch(reinterpret_cast<const void*>(row_contig ? f.rows : f.cols),
+                dim3(row_blocks, (unsigned)(kp / kKStep)), dim3(256), s, argv);
+}
+
+int launch_fill(const void* fn, int32_t* p, int64_t n, hipStream_t s) {
+  if (n == 0) return MDG_SUCCESS;
+  void* argv[] = {&p, &n};
+  const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  return launch(fn, dim3((unsigned)blocks), dim3(256), s, argv);
 }
 
 }  // namespace mdg_split_impl
@@ -440,8 +466,13 @@ int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const dou
   if (ld < max1(need_ld)) return 6;
   if (nslices < 1 || nslices > kMaxSlices) return 7;
   if (rows > 0 && (slices == nullptr || exponents == nullptr)) return 8;
-  return launch_slices(kFns[nslices], row_contig, X, ld, rows, k, kpad(k), slices, exponents,
-                       static_cast<hipStream_t>(stream));
+  if (rows == 0) return MDG_SUCCESS;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), exponents, rows, s);
+  if (st) return st;
+  st = launch_slices(kFns[nslices], row_contig, X, ld, rows, k, kpad(k), slices, exponents, s);
+  if (st) return st;
+  return launch_fill(reinterpret_cast<const void*>(&decode_exponents_kernel), exponents, rows, s);
 }
 
 int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
@@ -483,7 +514,11 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
   int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
   const Fns& f = kFns[nslices];
-  int st = launch_slices(f, is_trans(transa), A, lda, m, k, L.kp, as, ea, s);
+  // ea and eb are adjacent: zero both encoded exponent arrays in one launch
+  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), ea,
+                       (L.total - L.ea_off) / 4, s);
+  if (st) return st;
+  st = launch_slices(f, is_trans(transa), A, lda, m, k, L.kp, as, ea, s);
   if (st) return st;
   st = launch_slices(f, is_notrans(transb), B, ldb, n, k, L.kp, bs, eb, s);
   if (st) return st;

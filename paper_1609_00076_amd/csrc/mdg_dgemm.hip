@@ -85,9 +85,10 @@ struct LdsLayout {
 // XCD-aware tile order. Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
 // its own L2; the remap gives each XCD a contiguous run of tiles, and within a run tiles are
 // visited in column groups of GROUP tile-rows so that co-resident workgroups share A and B panels.
+template <int GROUP = 8>
 __device__ __forceinline__ void tile_coords(int wg, int nwg, int tiles_m, int tiles_n, int& tm,
                                             int& tn) {
-  constexpr int XCDS = 8, GROUP = 8;
+  constexpr int XCDS = 8;
   int t = wg;
   if (nwg % XCDS == 0) t = (wg % XCDS) * (nwg / XCDS) + wg / XCDS;
   int per_group = GROUP * tiles_n;
@@ -377,6 +378,10 @@ struct RingCfg {
   // they overlap; 1: MFMAs interleaved one by one with the direct loads and fragment reads, so
   // that the matrix pipe restarts at once after a barrier and LDS traffic is spread out.
   static constexpr int SCHED = SCHED_;
+  // Tile-rows per column group of the XCD-aware tile order: the 32 tiles resident on an XCD then
+  // span GROUP tile-rows and 32 / GROUP tile-columns; 4 x 8 tiles of 256 x 128 touch the fewest
+  // rows of op(A) plus columns of op(B) per k-panel (1024 + 1024).
+  static constexpr int GROUP = MT > NT ? 4 : 8;
   static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
   static constexpr int WAVES = WAVES_M * WAVES_N;
@@ -669,7 +674,7 @@ __global__ void __launch_bounds__(R::THREADS) __attribute__((amdgpu_waves_per_eu
 dgemm_ring_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) double smem[R::LDS_DOUBLES];
   int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  tile_coords<R::GROUP>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
   ring_tile<R, TA, TB>(g, tm, tn, smem);
 }
 
@@ -751,8 +756,8 @@ constexpr Variant make_variant(const char* name, Eff e) {
                   {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
 }
 
-// Efficiencies are the measured TFLOP/s of each variant at m = n = k = 8192..16384 (all four
-// transpose cases averaged) divided by 78.6.
+// Efficiencies are the measured TFLOP/s of each variant at m = n = k = 8192..16384 divided by
+// 78.6 (per transpose case where given as four numbers, NN NT TN TT).
 const Variant kVariants[] = {
     make_variant<Big>("mfma_f64_128x128x16_w64x64", 795),
     make_variant<Small>("mfma_f64_64x64x16_w32x32", 760),
@@ -771,10 +776,10 @@ const Variant kVariants[] = {
     make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 0),
     make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
     make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
-    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(925, 925, 918, 918)),
+    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(932, 924, 926, 931)),
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
-    make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(905, 905, 930, 930)),
+    make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(917, 923, 942, 941)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

@@ -205,6 +205,16 @@ __device__ __forceinline__ int swz(int row, int chunk) {
   return row * kStageRow + ((chunk ^ (((row >> 1) ^ (row >> 3)) & 3)) << 4);
 }
 
+// N times: M MFMAs, then one instruction of class MASK (a sched_group_barrier pattern).
+template <int MASK, int M, int N>
+__device__ __forceinline__ void sched_interleave() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, M, 0);
+    __builtin_amdgcn_sched_group_barrier(MASK, 1, 0);
+    sched_interleave<MASK, M, N - 1>();
+  }
+}
+
 // 8 waves (2 per SIMD) on a 64x64 tile: wave (wm, wn) with wm in 0..1, wn in 0..3 owns rows
 // 32*wm .. +31 (RB = 2 blocks) and columns 16*wn .. +15 (one block). Per k-step a wave holds the S
 // B-fragments of its column block and streams the A-fragments slice by slice.
@@ -300,6 +310,11 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
     constexpr bool STEADY = decltype(steady_tag)::value;
     const int buf = ks & 1;
     if (STEADY || ks + 2 < nsteps) fetch(spare, (int64_t)(ks + 2));
+    // Buffer buf^1 was last read before the previous barrier, so step ks+1 can be staged into
+    // it now, while this step's MFMAs run (up to 8 slices; beyond, the registers this keeps
+    // live at once would spill, and staging stays at the end of the step).
+    constexpr bool kEarly = S <= 8;
+    if (kEarly && (STEADY || ks + 1 < nsteps)) stage(next, buf ^ 1);
 
     v4i bf[S];
 #pragma unroll
@@ -320,7 +335,13 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
       fold();
       since_fold = 0;
     }
-    if (STEADY || ks + 1 < nsteps) stage(next, buf ^ 1);
+    if (!kEarly && (STEADY || ks + 1 < nsteps)) stage(next, buf ^ 1);
+    if (kEarly && STEADY) {
+      // MFMAs interleaved one by one with this step's global loads, then two by two with the
+      // staging writes (0x008 MFMA, 0x020 VMEM read, 0x200 DS write).
+      sched_interleave<0x020, 1, S>();
+      sched_interleave<0x200, 2, S>();
+    }
     __syncthreads();
   };
   using steady_t = std::integral_constant<bool, true>;

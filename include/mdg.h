@@ -59,9 +59,9 @@ extern "C" {
 #define MDG_ERR_HIP (-1)     /* a HIP call failed (no device, launch error) */
 #define MDG_ERR_VARIANT (-2) /* unknown kernel variant id, or one unfit for the arguments */
 #define MDG_ERR_DEVICE (-3)  /* the current device is not gfx950 */
-#define MDG_ERR_SIZE (-4)    /* m, n too large for one launch's grid, or a leading dimension of
-                                2^29 / (tile rows + 1) elements or more (one k-panel of a tile
-                                would span 4 GiB of byte offsets) */
+#define MDG_ERR_SIZE (-4)    /* m, n too large for one launch's grid, or a leading dimension so
+                                large that the part of one k-panel inside the matrix spans 4 GiB
+                                or more (the kernels address it by 32-bit byte offsets) */
 
 #define MDG_VARIANT_AUTO (-1)
 

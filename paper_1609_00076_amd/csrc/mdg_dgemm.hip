@@ -864,12 +864,22 @@ bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
 int64_t max1(int64_t x) { return x > 1 ? x : 1; }
 
 // Argument checks in dgemm argument order; 0 or the 1-based position of the first bad argument.
-// Every kernel addresses the elements of one k-panel by 32-bit byte offsets from the panel origin;
-// a panel spans at most max(mt, nt) leading dimensions (plus less than one), so this bound keeps
-// every offset below 4 GiB.
-bool panel_offsets_fit(int64_t tile_rows, int64_t lda, int64_t ldb) {
-  const int64_t ld = lda > ldb ? lda : ldb;
-  return (tile_rows + 1) * ld < ((int64_t)1 << 29);
+// Every kernel addresses the elements of one k-panel by 32-bit byte offsets from the panel origin
+// (loads of up to 16 bytes). For the rows and k-indices inside the matrix those offsets must not
+// wrap: at most (min(kt, k) - 1) * ld + tile_rows elements for an operand contiguous along its
+// tile rows, (min(tile_rows, rows) - 1) * ld + kt for one contiguous along k. (Tile rows beyond
+// the matrix may wrap: they read other data of the same storage and feed only outputs that are
+// never stored.)
+bool operand_offsets_fit(bool contig_k, int64_t tile_rows, int64_t rows, int64_t kt, int64_t k,
+                         int64_t ld) {
+  const int64_t span = contig_k ? ((tile_rows < rows ? tile_rows : rows) - 1) * ld + kt
+                                : ((kt < k ? kt : k) - 1) * ld + tile_rows;
+  return span * 8 + 16 <= ((int64_t)1 << 32);
+}
+
+bool panel_offsets_fit(bool ta, bool tb, int64_t mt, int64_t nt, int64_t kt, int64_t m, int64_t n,
+                       int64_t k, int64_t lda, int64_t ldb) {
+  return operand_offsets_fit(ta, mt, m, kt, k, lda) && operand_offsets_fit(!tb, nt, n, kt, k, ldb);
 }
 
 int check_args(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
@@ -1037,6 +1047,18 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   const bool no_product = (alpha == 0.0 || k == 0);
   if (no_product && beta == 1.0) return MDG_SUCCESS;
 
+  int vid = -1;
+  if (!no_product) {  // host-side checks of the launch shape, before any HIP call
+    vid = (variant == MDG_VARIANT_AUTO)
+              ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
+              : variant;
+    const Variant& v = kVariants[vid];
+    if (ceil_div(m, v.mt) * ceil_div(n, v.nt) > (int64_t)INT32_MAX / 1024)
+      return MDG_ERR_SIZE;  // beyond one launch's grid
+    if (!panel_offsets_fit(is_trans(transa), is_trans(transb), v.mt, v.nt, v.kt, m, n, k, lda,
+                           ldb))
+      return MDG_ERR_SIZE;
+  }
   const int dc = device_check();
   if (dc) return dc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1048,14 +1070,9 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
                   s, m, n, beta, C, ldc);
   }
 
-  const int vid = (variant == MDG_VARIANT_AUTO)
-                      ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
-                      : variant;
   const Variant& v = kVariants[vid];
   const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
   const int64_t tiles = tiles_m * tiles_n;
-  if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;  // beyond one launch's grid
-  if (!panel_offsets_fit(v.mt > v.nt ? v.mt : v.nt, lda, ldb)) return MDG_ERR_SIZE;
   const int64_t rows_a = is_trans(transa) ? k : m, cols_a = is_trans(transa) ? m : k;
   const int64_t rows_b = is_trans(transb) ? n : k, cols_b = is_trans(transb) ? k : n;
   GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C,
@@ -1141,7 +1158,8 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_
     o.tiles_m = ntiles ? (int32_t)ceil_div(d.m, mt) : 0;
     o.tiles_n = ntiles ? (int32_t)ceil_div(d.n, nt) : 0;
     if (ntiles && (o.tiles_m > INT32_MAX / 2 || o.tiles_n > INT32_MAX / 2 ||
-                   !panel_offsets_fit(mt > nt ? mt : nt, d.lda, d.ldb))) {
+                   (d.alpha != 0.0 && d.k > 0 &&
+                    !panel_offsets_fit(ta, tb, mt, nt, 16, d.m, d.n, d.k, d.lda, d.ldb)))) {
       if (bad_index) *bad_index = i;
       return MDG_ERR_SIZE;
     }

@@ -105,3 +105,26 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         b.mdg_version()
+
+
+def test_leading_dimension_offset_guard_is_host_side_and_exact():
+    """The panel-offset guard refuses only what the 32-bit panel offsets cannot address, and it
+    does so on the host, before any HIP call (raw addresses: nothing is dereferenced)."""
+    big = 1 << 28   # 2^28 elements: two such rows of a panel already span 4 GiB of bytes
+    fake = 1 << 40  # never dereferenced
+    # op(A) = A^T stored k x m: 300 rows of op(A) strided by lda
+    st = mdg.mdg_dgemm("T", "N", 300, 64, 64, 1.0, fake, big, fake, 64, 0.0, fake, 300)
+    assert st == -4, mdg.mdg_status_string(st)
+    # A stored m x k: 64 k-columns strided by lda
+    st = mdg.mdg_dgemm("N", "N", 64, 64, 64, 1.0, fake, big, fake, 64, 0.0, fake, 64)
+    assert st == -4
+    # op(B) columns strided by ldb (B stored k x n)
+    st = mdg.mdg_dgemm("N", "N", 64, 300, 64, 1.0, fake, 64, fake, big, 0.0, fake, 64)
+    assert st == -4
+    # one row and one k-index: nothing inside the matrix is more than one element away, so the
+    # guard lets it through (here the call then stops at the device check: no GPU)
+    st = mdg.mdg_dgemm("T", "T", 1, 1, 1, 1.0, fake, big, fake, big, 0.0, fake, 1)
+    assert st != -4 and st < 0
+    # alpha = 0: A and B are not read, so their leading dimensions do not matter
+    st = mdg.mdg_dgemm("T", "N", 300, 64, 64, 0.0, fake, big, fake, 64, 1.0, fake, 300)
+    assert st == 0  # quick return (beta = 1)

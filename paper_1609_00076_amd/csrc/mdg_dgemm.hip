@@ -85,12 +85,15 @@ struct LdsLayout {
 // XCD-aware tile order. Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each with
 // its own L2; the remap gives each XCD a contiguous run of tiles, and within a run tiles are
 // visited in column groups of GROUP tile-rows so that co-resident workgroups share A and B panels.
+// The host rounds the grid up to a multiple of 8 (kXcds); returns false for the padding
+// workgroups, which then exit at once.
+constexpr int kXcds = 8;
+
 template <int GROUP = 8>
-__device__ __forceinline__ void tile_coords(int wg, int nwg, int tiles_m, int tiles_n, int& tm,
+__device__ __forceinline__ bool tile_coords(int wg, int nwg, int tiles_m, int tiles_n, int& tm,
                                             int& tn) {
-  constexpr int XCDS = 8;
-  int t = wg;
-  if (nwg % XCDS == 0) t = (wg % XCDS) * (nwg / XCDS) + wg / XCDS;
+  const int t = (wg % kXcds) * (nwg / kXcds) + wg / kXcds;
+  if (t >= tiles_m * tiles_n) return false;
   int per_group = GROUP * tiles_n;
   int g = t / per_group;
   int first_m = g * GROUP;
@@ -98,6 +101,7 @@ __device__ __forceinline__ void tile_coords(int wg, int nwg, int tiles_m, int ti
   int r = t - g * per_group;
   tm = first_m + r % gsize;
   tn = r / gsize;
+  return true;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -335,7 +339,7 @@ __global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu
 dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ double smem[tile_lds_doubles<C, TA, TB>()];
   int tm, tn;
-  tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  if (!tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
   gemm_tile<C, TA, TB>(g, tm, tn, smem);
 }
 
@@ -674,7 +678,7 @@ __global__ void __launch_bounds__(R::THREADS) __attribute__((amdgpu_waves_per_eu
 dgemm_ring_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) double smem[R::LDS_DOUBLES];
   int tm, tn;
-  tile_coords<R::GROUP>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+  if (!tile_coords<R::GROUP>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
   ring_tile<R, TA, TB>(g, tm, tn, smem);
 }
 
@@ -1078,7 +1082,8 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C,
              (cols_a - 1) * lda + rows_a, (cols_b - 1) * ldb + rows_b};
   KernelFn fn = v.fn[is_trans(transa) ? 1 : 0][is_trans(transb) ? 1 : 0];
-  return launch(reinterpret_cast<const void*>(fn), dim3((unsigned)tiles), dim3(v.threads), s, g,
+  const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;  // see tile_coords
+  return launch(reinterpret_cast<const void*>(fn), dim3((unsigned)grid), dim3(v.threads), s, g,
                 (int)tiles_m, (int)tiles_n);
 }
 

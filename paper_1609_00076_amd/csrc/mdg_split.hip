@@ -233,9 +233,10 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
 
   // Tile order: each XCD gets a contiguous run of tiles, visited in column groups of 8 tile-rows,
   // so the 32 workgroups resident on an XCD cover an 8 x 4 block and share A and B panels in L2.
-  int t = blockIdx.x;
+  // The host rounds the grid up to a multiple of 8; the padding workgroups exit here.
   const int nwg = gridDim.x;
-  if (nwg % 8 == 0) t = (t % 8) * (nwg / 8) + t / 8;
+  const int t = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  if (t >= tiles_m * tiles_n) return;
   constexpr int kGroup = 8;
   const int per_group = kGroup * tiles_n;
   const int grp = t / per_group, first_m = grp * kGroup;
@@ -552,7 +553,7 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   SplitArgs g{m, n, L.kp, alpha, beta, C, ldc, as, bs, ea, eb, flush};
   int tm = (int)tiles_m, tn = (int)tiles_n;
   void* argv[] = {&g, &tm, &tn};
-  return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)(tiles_m * tiles_n)),
+  return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)((tiles_m * tiles_n + 7) / 8 * 8)),
                 dim3(kThreads), s, argv);
 }
 

@@ -392,13 +392,16 @@ struct RingCfg {
   static constexpr int THREADS = WAVES * 64;
   static constexpr int BM = WM / 16, BN = WN / 16;
   static constexpr int PAIRS = KT / 8;  // k-pairs of MFMA substeps per panel
-  static constexpr int ROW_A = MT + 8, ROW_B = NT + 8;  // k-major row strides (doubles)
+  // k-major row strides (doubles): 8 doubles of padding, except for 64-row tiles, whose 1 KB
+  // direct loads fill two k-rows at once and use the XOR placement of kmaj_index instead.
+  static constexpr int ROW_A = MT == 64 ? 64 : MT + 8, ROW_B = NT == 64 ? 64 : NT + 8;
   static constexpr int STAGE_A = KT * ROW_A, STAGE_B = KT * ROW_B;
   static constexpr int STAGE = STAGE_A + STAGE_B;
   static constexpr int LDS_DOUBLES = STAGES * STAGE;
   static constexpr int A_LOADS = MT * KT / 128 / WAVES, B_LOADS = NT * KT / 128 / WAVES;
   static constexpr int LOADS = A_LOADS + B_LOADS;  // direct loads per wave per panel
-  static_assert(MT % 128 == 0 && NT % 128 == 0, "k-major chunks are 128-row pieces of a k-row");
+  static_assert((MT % 128 == 0 || MT == 64) && (NT % 128 == 0 || NT == 64),
+                "k-major chunks are 128-row pieces of a k-row, or two k-rows of a 64-row tile");
   static_assert((MT * KT / 128) % WAVES == 0 && (NT * KT / 128) % WAVES == 0, "chunk split");
   static_assert(MT % WM == 0 && NT % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave grid");
   static_assert(STAGES >= 2 && STAGES <= 4 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
@@ -406,6 +409,17 @@ struct RingCfg {
 };
 
 __device__ __forceinline__ int ring_swz(int row) { return (row & 7) ^ ((row >> 3) & 1); }
+
+// LDS index (doubles, within an operand's stage) of element (k-row q, row i) of a k-major panel
+// with ROWS rows and row stride ROW. For ROWS = 64 the rows are unpadded and k-rows whose index
+// has bit 1 set are stored with bit 4 of the row index flipped (a 128-byte shift), so the
+// fragment reads of k-rows two apart, issued by the two halves of a 32-lane phase, fall in
+// opposite halves of the LDS banks.
+template <int ROWS, int ROW>
+__device__ __forceinline__ int kmaj_index(int q, int i) {
+  if constexpr (ROWS == 64) return q * 64 + (i ^ (16 * ((q >> 1) & 1)));
+  else return q * ROW + i;
+}
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
@@ -459,7 +473,14 @@ template <class R, int ROWS, int ROW, bool CONTIG_K>
 __device__ __forceinline__ void ring_map(int wave, int lane, int u, int64_t ld, uint32_t& off,
                                          int& lds) {
   const int c = wave + R::WAVES * u;
-  if (!CONTIG_K) {
+  if (!CONTIG_K && ROWS == 64) {
+    // chunk c holds k-rows 2c (lanes 0-31) and 2c+1 (lanes 32-63); lane l writes doubles
+    // 2(l & 31), +1 of its k-row, which kmaj_index assigns to rows i, i+1 below
+    const int q = 2 * c + (lane >> 5);
+    const int i = 2 * ((lane & 31) ^ (8 * ((q >> 1) & 1)));
+    off = (uint32_t)((i + (int64_t)q * ld) * 8);
+    lds = c * 128;
+  } else if (!CONTIG_K) {
     constexpr int per_row = ROWS / 128;
     const int q = c / per_row, part = c % per_row;
     const int i = part * 128 + 2 * lane;
@@ -479,12 +500,18 @@ __device__ __forceinline__ void ring_mask_tail(double* st, int k_left) {
   double* As = st;
   double* Bs = st + R::STAGE_A;
   for (int e = threadIdx.x; e < R::MT * R::KT; e += R::THREADS) {
-    if (!TA) { const int q = e / R::MT, i = e % R::MT; if (q >= k_left) As[q * R::ROW_A + i] = 0.0; }
+    if (!TA) {
+      const int q = e / R::MT, i = e % R::MT;
+      if (q >= k_left) As[kmaj_index<R::MT, R::ROW_A>(q, i)] = 0.0;
+    }
     else { const int i = e / R::KT, q = e % R::KT;
            if (q >= k_left) As[i * R::KT + 2 * ((q >> 1) ^ ring_swz(i)) + (q & 1)] = 0.0; }
   }
   for (int e = threadIdx.x; e < R::NT * R::KT; e += R::THREADS) {
-    if (TB) { const int q = e / R::NT, j = e % R::NT; if (q >= k_left) Bs[q * R::ROW_B + j] = 0.0; }
+    if (TB) {
+      const int q = e / R::NT, j = e % R::NT;
+      if (q >= k_left) Bs[kmaj_index<R::NT, R::ROW_B>(q, j)] = 0.0;
+    }
     else { const int j = e / R::KT, q = e % R::KT;
            if (q >= k_left) Bs[j * R::KT + 2 * ((q >> 1) ^ ring_swz(j)) + (q & 1)] = 0.0; }
   }
@@ -535,8 +562,15 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
   // Fragment addresses (doubles from the stage base) of this lane for pair 0; pair h adds h * 8
   // k-rows (k-major) or flips slot bit 2 (row-major: slot (4h + c) ^ f = (4h) ^ (c ^ f)).
   const int ai = wave_m * R::WM + l16, bj = wave_n * R::WN + l16;
+  // k-major: this lane's k-row 2*lq (+ 8h + e) and row ai (bj) of block 0. Block b adds 16 rows;
+  // in a 64-row tile k-rows 2*lq + 8h + e all have bit 1 equal to lq & 1, so kmaj_index flips
+  // bit 4 of the row for odd lq (the wave's rows start at a multiple of 32, so bit 4 of
+  // ai + 16b is the block's parity): block b is read at 16 * (b ^ (lq & 1)).
   const int a_kmaj = 2 * lq * R::ROW_A + ai;
   const int b_kmaj = R::STAGE_A + 2 * lq * R::ROW_B + bj;
+  const int kflip = lq & 1;
+  static_assert(R::MT != 64 || R::WM % 32 == 0, "64-row tiles: wave rows start at multiples of 32");
+  static_assert(R::NT != 64 || R::WN % 32 == 0, "64-row tiles: wave rows start at multiples of 32");
   const int a_rmaj = ai * R::KT + 2 * (lq ^ ring_swz(l16));
   const int b_rmaj = R::STAGE_A + bj * R::KT + 2 * (lq ^ ring_swz(l16));
 
@@ -545,7 +579,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
     for (int b = 0; b < R::BM; ++b) {
       if (!TA) {
-        const double* p = st + a_kmaj + 8 * h * R::ROW_A + 16 * b;
+        const double* p = st + a_kmaj + 8 * h * R::ROW_A + 16 * (R::MT == 64 ? (b ^ kflip) : b);
         fa[b] = (d2){p[0], p[R::ROW_A]};
       } else {
         fa[b] = *reinterpret_cast<const d2*>(st + ((a_rmaj + 16 * b * R::KT) ^ (8 * h)));
@@ -554,7 +588,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
     for (int b = 0; b < R::BN; ++b) {
       if (TB) {
-        const double* p = st + b_kmaj + 8 * h * R::ROW_B + 16 * b;
+        const double* p = st + b_kmaj + 8 * h * R::ROW_B + 16 * (R::NT == 64 ? (b ^ kflip) : b);
         fb[b] = (d2){p[0], p[R::ROW_B]};
       } else {
         fb[b] = *reinterpret_cast<const d2*>(st + ((b_rmaj + 16 * b * R::KT) ^ (8 * h)));
@@ -706,6 +740,9 @@ using Ring256i = RingCfg<256, 128, 64, 32, 3, 4, 1>;    // Ring256, interleaved 
 using Ring128x4i = RingCfg<128, 128, 32, 32, 4, 4, 1>;  // Ring128x4, interleaved issue
 using Ring128wi = RingCfg<128, 256, 32, 64, 3, 4, 1>;   // Ring128w, interleaved issue
 using Ring256wi = RingCfg<256, 128, 64, 64, 3, 2, 1>;   // 8 waves of 64x64, interleaved issue
+using Ring64s3 = RingCfg<64, 64, 32, 32, 3, 3, 1>;      // 4 waves of 32x32, 3 stages, 3 WGs per CU
+using Ring64s4 = RingCfg<64, 64, 32, 32, 4, 2, 1>;      // 4 stages, 2 WGs per CU
+using Ring128x64 = RingCfg<128, 64, 32, 32, 3, 4, 1>;   // 8 waves of 32x32, 3 stages, 2 WGs per CU
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -784,6 +821,9 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
     make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(917, 923, 942, 941)),
+    make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811)),
+    make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
+    make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

@@ -755,6 +755,9 @@ struct Variant {
   int eff_permil[2][2];  // [transa][transb]: measured share of the FP64 MFMA peak on large
                          // square shapes, per mille; 0 keeps the variant out of the automatic
                          // choice
+  int short_k_permil;    // the same share measured on m = n = 8192, k = 64 (HBM-bound: the old
+                         // C streams in and out); 0 keeps the variant out of the choice for
+                         // k <= kShortK
   KernelFn fn[2][2];  // [transa][transb]
 };
 
@@ -774,25 +777,25 @@ struct Eff {
 };
 
 template <class R>
-constexpr Variant make_ring_variant(const char* name, Eff e) {
+constexpr Variant make_ring_variant(const char* name, Eff e, int short_k = 0) {
   constexpr int by_lds = kLdsPerCU / (R::LDS_DOUBLES * 8);
   constexpr int by_waves = (R::MIN_WAVES_PER_EU * 4) / R::WAVES;
   constexpr int wgs = by_lds < by_waves ? by_lds : by_waves;
   return Variant{name, R::MT, R::NT, R::KT, R::THREADS, wgs > 0 ? wgs : 1,
-                 {{e.nn, e.nt}, {e.tn, e.tt}},
+                 {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
                  {{dgemm_ring_kernel<R, false, false>, dgemm_ring_kernel<R, false, true>},
                   {dgemm_ring_kernel<R, true, false>, dgemm_ring_kernel<R, true, true>}}};
 }
 
 template <class C>
-constexpr Variant make_variant(const char* name, Eff e) {
+constexpr Variant make_variant(const char* name, Eff e, int short_k = 0) {
   return Variant{name,
                  C::MT,
                  C::NT,
                  C::KT,
                  C::THREADS,
                  resident_wgs<C>() > 0 ? resident_wgs<C>() : 1,
-                 {{e.nn, e.nt}, {e.tn, e.tt}},
+                 {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
                  {{dgemm_mfma_kernel<C, false, false>, dgemm_mfma_kernel<C, false, true>},
                   {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
 }
@@ -801,14 +804,14 @@ constexpr Variant make_variant(const char* name, Eff e) {
 // 78.6 (per transpose case where given as four numbers, NN NT TN TT).
 const Variant kVariants[] = {
     make_variant<Big>("mfma_f64_128x128x16_w64x64", 795),
-    make_variant<Small>("mfma_f64_64x64x16_w32x32", 760),
+    make_variant<Small>("mfma_f64_64x64x16_w32x32", 760, 360),
     make_variant<Big8a>("mfma_f64_128x128x16_w32x64", 848),
     make_variant<Big8b>("mfma_f64_128x128x16_w64x32", 853),
     make_variant<Tall>("mfma_f64_256x128x16_w64x64", 816),
     make_variant<Wide>("mfma_f64_128x256x16_w64x64", 816),
-    make_variant<Big16>("mfma_f64_128x128x16_w32x32", 865),
+    make_variant<Big16>("mfma_f64_128x128x16_w32x32", 865, 440),
     make_variant<Tall16>("mfma_f64_256x128x16_w64x32", 847),
-    make_variant<Mid8>("mfma_f64_128x64x16_w32x32", 790),
+    make_variant<Mid8>("mfma_f64_128x64x16_w32x32", 790, 446),
     make_variant<Big16p>("mfma_f64_128x128x16_w32x32_pad", 860),
     make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 0),
     make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
@@ -821,9 +824,9 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
     make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(917, 923, 942, 941)),
-    make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811)),
+    make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811), 393),
     make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
-    make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868)),
+    make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868), 400),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -958,20 +961,26 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // kTileOverheadK / resident k-steps stands for a tile's prologue and epilogue (old C read, C
 // written), which co-resident workgroups partly overlap. The smallest estimate wins; ties go to
 // the earlier entry.
+// For k <= kShortK the GEMM is bound by the old C streaming through HBM rather than by the
+// MFMAs, and the variants are ranked by their efficiency measured on such a shape (which already
+// includes the epilogue).
 constexpr double kTileOverheadK = 128.0;
+constexpr int64_t kShortK = 256;
 
 int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
   int best = 0;
   double best_cost = 0.0;
+  const bool short_k = k <= kShortK;
   for (int v = 0; v < kNumVariants; ++v) {
     const Variant& var = kVariants[v];
-    const int eff = var.eff_permil[ta][tb];
+    const int eff = short_k ? var.short_k_permil : var.eff_permil[ta][tb];
     if (eff <= 0) continue;
     const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
     const int64_t per_cu = ceil_div(tiles, kCUs);
     const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
     const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
-    const double cost = (double)per_cu * var.mt * var.nt * ((double)k + kTileOverheadK / resident) /
+    const double overhead = short_k ? 0.0 : kTileOverheadK / resident;
+    const double cost = (double)per_cu * var.mt * var.nt * ((double)k + overhead) /
                         (eff * 1e-3 * occupancy);
     if (best_cost == 0.0 || cost < best_cost) {
       best = v;

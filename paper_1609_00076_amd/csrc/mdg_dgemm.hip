@@ -473,14 +473,14 @@ template <class R, int ROWS, int ROW, bool CONTIG_K>
 __device__ __forceinline__ void ring_map(int wave, int lane, int u, int64_t ld, uint32_t& off,
                                          int& lds) {
   const int c = wave + R::WAVES * u;
-  if (!CONTIG_K && ROWS == 64) {
+  if constexpr (!CONTIG_K && ROWS == 64) {
     // chunk c holds k-rows 2c (lanes 0-31) and 2c+1 (lanes 32-63); lane l writes doubles
     // 2(l & 31), +1 of its k-row, which kmaj_index assigns to rows i, i+1 below
     const int q = 2 * c + (lane >> 5);
     const int i = 2 * ((lane & 31) ^ (8 * ((q >> 1) & 1)));
     off = (uint32_t)((i + (int64_t)q * ld) * 8);
     lds = c * 128;
-  } else if (!CONTIG_K) {
+  } else if constexpr (!CONTIG_K) {
     constexpr int per_row = ROWS / 128;
     const int q = c / per_row, part = c % per_row;
     const int i = part * 128 + 2 * lane;

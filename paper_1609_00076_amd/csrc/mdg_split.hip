@@ -11,8 +11,9 @@
 //      v_mfma_i32_16x16x64_i8, summed per anti-diagonal d = s + t;
 //   4. recombine in binary64: C' = sum_d 2^-7d sum_{s+t=d} P_st, unscale by 2^(e_i + f_j), and
 //      apply alpha and beta in binary64.
-// Slices live in a caller-provided workspace, k-contiguous per row of op(A) and per column of
-// op(B), padded with zeros to a multiple of 64 in k.
+// Slices live in a caller-provided workspace as 64-row x 64-k tiles of bytes (each row of op(A),
+// each column of op(B), holds 64 consecutive k in one 64-byte run), padded with zeros to multiples
+// of 64 in rows and in k.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

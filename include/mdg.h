@@ -113,9 +113,9 @@ const char *mdg_status_string(int status);
  *
  * op(A) is scaled row by row and op(B) column by column by powers of two so every entry lies in
  * (-1, 1), each scaled entry is split exactly into `nslices` int8 slices of 7 bits, the products
- * of slice pairs (s, t) with s + t <= nslices + 1 are formed exactly in INT32 on
- * v_mfma_i32_16x16x64_i8, and the sum is recombined, unscaled and combined with alpha, beta and
- * the old C in binary64. The result approximates the FP64 product: the error is about
+ * of slice pairs (s, t) with s + t <= nslices + 1 are formed exactly in INT32 on the INT8
+ * matrix cores (v_mfma_i32_32x32x32_i8 up to 8 slices, v_mfma_i32_16x16x64_i8 beyond), and the
+ * sum is recombined, unscaled and combined with alpha, beta and the old C in binary64. The result approximates the FP64 product: the error is about
  * k * 2^(-7*nslices) times the product of the row and column maxima, so entries whose magnitudes
  * spread widely within a row or column need more slices. Measured for entries u * 2^e, e uniform in
  * [-phi, phi]: at k = 8192, nslices = 7 (phi = 0), 8 (phi = 8), 10 (phi = 32) keep
@@ -152,10 +152,13 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
 /*
  * The slicing step alone, for one operand: operand 0 slices the rows of op(A) (rows = m, trans =
  * transa, X = A, ld = lda), operand 1 the columns of op(B) (rows = n, trans = transb, X = B,
- * ld = ldb). With rp = rows and kp = k, each rounded up to a multiple of 64, writes slice s of
- * entry (r, p) at slices[s*rp*kp + (p/64)*rp*64 + r*64 + p%64] for r < rp, p < kp (zero for
- * r >= rows or p >= k: one 64-row block of one slice for one 64-deep k-step is 4 KiB of
- * contiguous bytes), so `slices` holds nslices*rp*kp bytes; and exponents[r] = e with
+ * ld = ldb). With rp = rows rounded up to a multiple of 128 and kp = k rounded up to a multiple
+ * of 64, writes slice s of entry (r, p) at
+ *   slices[s*rp*kp + (p/32)*rp*32 + (r/32)*1024 + 16*slot(r%32, (p/16)%2) + p%16],
+ *   slot(i, h) = 2*i + (h XOR (((i/4) XOR (i/8)) AND 1)),
+ * for r < rp, p < kp (zero for r >= rows or p >= k): each 32-deep k-panel of a slice is rp*32
+ * bytes, made of 1 KiB chunks of 32 rows in which row i keeps its two 16-byte halves at slots
+ * slot(i, 0) and slot(i, 1). `slices` holds nslices*rp*kp bytes; and exponents[r] = e with
  * max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row). Returns 0, or
  * 1 operand, 2 trans, 3 rows < 0, 4 k < 0, 5 X NULL, 6 ld too small, 7 nslices out of range,
  * 8 output NULL, or a negative runtime code.

@@ -260,7 +260,7 @@ def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents,
         if rows > 0 and k > 0 and ld >= max(1, k if row_contig else rows) else 0
     ok_s = 1 <= int(nslices) <= mdg_split_max_slices()
     xp = _ptr(X, need_x, "X")
-    rp = (int(rows) + 63) // 64 * 64
+    rp = (int(rows) + 127) // 128 * 128
     sp = _raw_ptr(slices, int(nslices) * rp * kp if ok_s and rows > 0 else 0, "slices")
     ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
     return load().mdg_split_slices(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),

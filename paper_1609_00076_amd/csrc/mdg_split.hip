@@ -44,14 +44,23 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, int64_t bytes) {
 // Slicing. X is a rows x k matrix given by its storage: x(r,p) = X[r*ld + p] when ROW_CONTIG
 // (op(A) with transa = T, op(B)^T with transb = N), else X[p*ld + r]. Output: exps[r] and the
 // slices in k-panel tiles: byte (s, r, p) at slice_offset(s, r, p) for r < rp (rows rounded up
-// to 64) and p < kp (k rounded up to 64), zero for r >= rows or p >= k. One 64-row block of one
-// slice for one 64-deep k-step is thus 4 KiB of contiguous bytes.
+// to 128) and p < kp (k rounded up to 64), zero for r >= rows or p >= k. Within slice s, the
+// 32 k-values p = 32c .. 32c+31 of all rp rows form panel c (rp * 32 bytes); the panel holds
+// 1 KiB chunks of 32 consecutive rows, and in a chunk row i keeps its two 16-byte halves h at
+// 16-byte slots row_slot(i, h). A chunk is what one wave moves into LDS with one direct load, and
+// the slot order makes the fragment reads of 8 or 16 consecutive rows hit distinct LDS banks.
 // ------------------------------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int64_t round64(int64_t x) { return (x + 63) / 64 * 64; }
+__host__ __device__ __forceinline__ int64_t round128(int64_t x) { return (x + 127) / 128 * 128; }
+
+__host__ __device__ __forceinline__ int row_slot(int i, int h) {  // i in 0..31, h in 0..1
+  return 2 * i + (h ^ (((i >> 2) ^ (i >> 3)) & 1));
+}
 
 __device__ __forceinline__ int64_t slice_offset(int s, int64_t r, int64_t p, int64_t rp,
                                                 int64_t kp) {
-  return (int64_t)s * rp * kp + (p >> 6) * rp * 64 + r * 64 + (p & 63);
+  return (int64_t)s * rp * kp + (p >> 5) * rp * 32 + (r >> 5) * 1024 +
+         16 * row_slot((int)(r & 31), (int)((p >> 4) & 1)) + (p & 15);
 }
 __device__ __forceinline__ int row_exponent(double mx) {
   int e = 0;
@@ -134,7 +143,8 @@ __global__ void __launch_bounds__(256) split_max_kernel(const double* X, int64_t
 
 // Pass 2: one 64 x 64 block (rows x k) per workgroup, staged through LDS so that the global reads
 // are 512-byte runs for either storage order; thread t then slices row t/4, k-values
-// 16*(t%4) .. +15 and writes S 16-byte groups, so each slice's 4 KiB tile is written whole.
+// 16*(t%4) .. +15 and writes S 16-byte groups, so a wave writes two 512-byte runs per slice.
+// The grid covers rp rows; blocks past the matrix write zero rows.
 template <int S, bool ROW_CONTIG>
 __global__ void __launch_bounds__(256) split_tile_kernel(const double* X, int64_t ld, int64_t rows,
                                                          int64_t k, int64_t kp, int8_t* out,
@@ -142,7 +152,7 @@ __global__ void __launch_bounds__(256) split_tile_kernel(const double* X, int64_
   __shared__ double tile[64][65];  // [row][k], one double of padding per row
   const int t = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * 64;
-  const int64_t rp = round64(rows);
+  const int64_t rp = round128(rows);
   if (!ROW_CONTIG) {
     const int r = t & 63;
 #pragma unroll
@@ -188,11 +198,11 @@ struct SplitArgs {
   double alpha, beta;
   double* C;
   int64_t ldc;
-  const int8_t* As;  // slices of op(A) in k-panel tiles (see slice_offset), rows rounded to 64
+  const int8_t* As;  // slices of op(A) in k-panel tiles (see slice_offset), rows rounded to 128
   const int8_t* Bs;  // slices of op(B)^T, the same way
   const int32_t* ea;  // encoded exponents (see decode_exponent)
   const int32_t* eb;
-  int flush_steps;   // k-steps of 64 after which the INT32 accumulators are folded into FP64
+  int flush_steps;   // k-steps after which the INT32 accumulators are folded into FP64
 };
 
 constexpr int kTile = 64;
@@ -204,6 +214,12 @@ constexpr int kSliceBytes = kTile * kStageRow;        // 4 KiB per slice per ope
 // lanes over 64 banks; each row keeps its four chunks, so the staging writes stay conflict-free.
 __device__ __forceinline__ int swz(int row, int chunk) {
   return row * kStageRow + ((chunk ^ (((row >> 1) ^ (row >> 3)) & 3)) << 4);
+}
+
+// N instructions of class MASK as one scheduling group.
+template <int MASK, int N>
+__device__ __forceinline__ void sched_group() {
+  if constexpr (N > 0) __builtin_amdgcn_sched_group_barrier(MASK, N, 0);
 }
 
 // N times: M MFMAs, then one instruction of class MASK (a sched_group_barrier pattern).
@@ -252,12 +268,15 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   const int ld_op = __builtin_amdgcn_readfirstlane(tid >> 8);
   const int ld_row = (tid & 255) >> 2, ld_chunk = tid & 3;
   // Each operand's slices are k-panel tiles: this thread's 16 bytes of k-step ks of slice s are at
-  // s * slice_stride + ks * step_stride + off0, and a wave's 64 loads cover 1 KiB of contiguous
-  // bytes (16 rows of one 4 KiB tile).
-  const int64_t rp = round64(ld_op ? g.n : g.m);
+  // s * slice_stride + ks * step_stride + off0, and a wave's 64 loads cover two 512-byte runs
+  // (16 rows of one 1 KiB chunk in each of the step's two 32-deep panels).
+  const int64_t rp = round128(ld_op ? g.n : g.m);
   const int64_t slice_stride = rp * g.kp, step_stride = rp * kKStep;
   const rsrc_t rsrc = make_rsrc(ld_op ? (const void*)g.Bs : (const void*)g.As, (int64_t)S * slice_stride);
-  const int64_t off0 = ((ld_op ? col0 : row0) + ld_row) * kKStep + ld_chunk * 16;
+  // k-chunk c of a 64-deep step lies in 32-deep panel c / 2, half c % 2
+  const int64_t ld_r = (ld_op ? col0 : row0) + ld_row;
+  const int64_t off0 = (ld_chunk >> 1) * rp * 32 + (ld_r >> 5) * 1024 +
+                       16 * row_slot((int)(ld_r & 31), ld_chunk & 1);
   const int st_off = swz(ld_row, ld_chunk);
 
   // Two register sets of staged data: the panel for step ks+2 is loaded while step ks computes,
@@ -377,35 +396,269 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Slice-product GEMM on v_mfma_i32_32x32x32_i8, for up to kMaxSlices32 slices.
+//
+// Workgroup: 128x64 tile of C, 8 waves (2 per SIMD) of 32x32. Per 32-deep k-step the S slices of
+// both operands (4 chunks of A and 2 of B per slice, 1 KiB each) go from the workspace straight
+// into LDS with direct loads (buffer_load ... lds: lane l's 16 bytes land at the wave-uniform base
+// plus 16 l, so a chunk keeps its global byte order, including the row_slot placement). Three LDS
+// stages form a ring: the loads for step t+3 go into step t's stage as soon as every wave holds
+// all of step t's fragments in registers, so a load has two k-steps to arrive.
+//
+// v_mfma_i32_32x32x32_i8(X, Y, Z): lane l supplies row l%32 of X (32x32) and column l%32 of Y
+// (32x32), 16 k-values each (the same k-order for both, so the product is exact whatever the
+// order), and holds D[8*(r/4) + 4*(l/32) + r%4][l%32] in accumulator r (checked on the GPU with an
+// in-bounds probe). With X = B_t^T and Y = A_s^T, D = (A_s B_t)^T: lane l holds
+// C(i0 + l%32, j0 + 8*(r/4) + 4*(l/32) + r%4), so each accumulator register covers 32 consecutive
+// rows of two columns.
+// ------------------------------------------------------------------------------------------------
+constexpr int kMaxSlices32 = 8;  // 3 stages of 6 KiB x S fit 160 KiB; accumulators fit 256 VGPRs
+constexpr int kMT32 = 128, kNT32 = 64, kKStep32 = 32, kChunk = 1024, kStages32 = 3;
+
+template <int S>
+struct Cfg32 {
+  static constexpr int A_CH = 4 * S, B_CH = 2 * S, CH = A_CH + B_CH;  // chunks per stage
+  static constexpr int LOADS = (CH + 7) / 8;  // direct loads per wave per stage (some may be idle)
+  static constexpr int STAGE = CH * kChunk;
+  static constexpr int TRASH = kStages32 * STAGE;  // 1 KiB that idle loads fill with zeros
+  static constexpr int SPLIT = S > 1 ? S / 2 : 1;  // slices multiplied before the mid-step barrier
+  static constexpr int HI = S - SPLIT;  // slices multiplied after it
+  static constexpr int PART2 = HI * (HI + 1) / 2;  // products after it
+  static_assert((kStages32 - 1) * LOADS <= 63, "vmcnt range");
+};
+
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+__device__ __forceinline__ void bare_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// s_waitcnt vmcnt(N) lgkmcnt(0), expcnt untouched. A plain __syncthreads would also wait for the
+// direct loads still in flight for later stages.
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+  static_assert(N >= 0 && N <= 63, "vmcnt");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+// The kernel body lives in a device function: the host pass then only sees the kernel's
+// signature, and emits its launch stub.
+template <int S>
+__device__ __forceinline__ void split32_tile(const SplitArgs& g, int tiles_m, int tiles_n,
+                                             int8_t* lds) {
+  using C = Cfg32<S>;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave_m = wave & 3, wave_n = wave >> 2;
+
+  // Tile order: each XCD gets a contiguous run of tiles, visited in column groups of 4 tile-rows
+  // (the 32 workgroups resident on an XCD cover a 4 x 8 block: 512 rows of A, 512 columns of B).
+  // The host rounds the grid up to a multiple of 8; the padding workgroups exit here.
+  const int nwg = gridDim.x;
+  const int t = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  if (t >= tiles_m * tiles_n) return;
+  constexpr int kGroup = 4;
+  const int per_group = kGroup * tiles_n;
+  const int grp = t / per_group, first_m = grp * kGroup;
+  const int gsize = min(tiles_m - first_m, kGroup);
+  const int rem = t - grp * per_group;
+  const int tm = first_m + rem % gsize, tn = rem / gsize;
+  const int64_t row0 = (int64_t)tm * kMT32, col0 = (int64_t)tn * kNT32;
+
+  // Direct loads: load u of wave w moves chunk c = 8u + w of the stage: c < A_CH is chunk c % 4
+  // (32 rows) of A slice c / 4, then B's chunks, then idle loads (out of range of an empty buffer,
+  // which reads zeros, into the trash chunk). The kind of each load is uniform within the wave.
+  const int64_t rpa = round128(g.m), rpb = round128(g.n);
+  const int64_t slice_a = rpa * g.kp, slice_b = rpb * g.kp;
+  const uint32_t step_a = (uint32_t)(rpa * kKStep32), step_b = (uint32_t)(rpb * kKStep32);
+  // Offsets stay below 2^32: the host keeps each operand's slice array under 4 GiB.
+  const int64_t bytes_a = (int64_t)S * slice_a, bytes_b = (int64_t)S * slice_b;
+  uint32_t voff[C::LOADS];
+#pragma unroll
+  for (int u = 0; u < C::LOADS; ++u) {
+    const int c = 8 * u + wave;
+    int64_t o = 0;
+    if (c < C::A_CH) o = (c >> 2) * slice_a + (row0 + 32 * (c & 3)) * kKStep32;
+    else if (c < C::CH) o = ((c - C::A_CH) >> 1) * slice_b + (col0 + 32 * ((c - C::A_CH) & 1)) * kKStep32;
+    voff[u] = (uint32_t)o + 16u * (uint32_t)lane;
+  }
+  auto issue = [&](int p) __attribute__((always_inline)) {
+    int8_t* st = lds + (p % kStages32) * C::STAGE;
+#pragma unroll
+    for (int u = 0; u < C::LOADS; ++u) {
+      const int c = 8 * u + wave;
+      const bool is_a = c < C::A_CH, is_b = !is_a && c < C::CH;
+      // scalar selects of base, size and k-step; the descriptor is built from them
+      const void* base = is_b ? (const void*)g.Bs : (const void*)g.As;
+      const int64_t bytes = is_a ? bytes_a : is_b ? bytes_b : 0;
+      const uint32_t soff = is_a ? (uint32_t)p * step_a : is_b ? (uint32_t)p * step_b : 0u;
+      int8_t* dst = (is_a || is_b) ? st + c * kChunk : lds + C::TRASH;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(make_rsrc(base, bytes), (lds_void_ptr)dst, 16, voff[u],
+                                               (int)soff, 0, 0);
+    }
+  };
+
+  // Fragment reads: lane l reads row l%32 of the wave's chunk, half l/32.
+  const int frag = 16 * row_slot(lane & 31, lane >> 5);
+  const int a_frag = wave_m * kChunk + frag;                   // + (4 s) KiB
+  const int b_frag = (C::A_CH + wave_n) * kChunk + frag;       // + (2 t) KiB
+  auto read_a = [&](const int8_t* st, int s) __attribute__((always_inline)) {
+    return *reinterpret_cast<const v4i*>(st + a_frag + 4 * s * kChunk);
+  };
+  v4i bf[S], a0;  // a step's B fragments and its first A fragment, read before the step starts
+  auto read_first = [&](const int8_t* st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < S; ++u) bf[u] = *reinterpret_cast<const v4i*>(st + b_frag + 2 * u * kChunk);
+    a0 = read_a(st, 0);
+  };
+
+  v16i acc[S];  // [diagonal d - 2]
+  double cf[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) cf[r] = 0.0;
+#pragma unroll
+  for (int d = 0; d < S; ++d)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[d][r] = 0;
+  auto fold = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        cf[r] += ldexp((double)acc[d][r], -kBeta * (d + 2));
+        acc[d][r] = 0;
+      }
+  };
+  // slice pairs (s+1, u+1), diagonal s + u + 2
+  auto mult = [&](int s, const v4i& a) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < S - s; ++u)
+      acc[s + u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[u], a, acc[s + u], 0, 0, 0);
+  };
+
+  const int nsteps = (int)(g.kp / kKStep32);  // >= 2: kp is a positive multiple of 64
+  const int pre = nsteps < kStages32 ? nsteps : kStages32;
+  for (int p = 0; p < pre; ++p) issue(p);
+  if (pre == 3) wait_vm_lgkm0<2 * C::LOADS>();
+  else wait_vm_lgkm0<C::LOADS>();
+  bare_barrier();
+  read_first(lds);
+  int since_fold = 0;
+
+  // One k-step from stage ts % 3. MID: 0 = the last step (no barrier), 1 = a barrier after the
+  // first SPLIT slices with no further loads to issue, 2 = a barrier, then the loads of step
+  // ts + 3 into this step's stage (every fragment of this step is in registers by then).
+  //   before the barrier: read the A fragments of slices 2..S while slice 1's products run
+  //     (B fragments read earliest first), then the products of slices 2..SPLIT;
+  //   after it: read the next step's B fragments that the remaining products no longer need and
+  //     its first A fragment, issue the loads, run the products of slices SPLIT+1..S, and read the
+  //     last B fragments as their final uses retire.
+  auto step = [&](auto mid_tag, int ts) __attribute__((always_inline)) {
+    constexpr int MID = decltype(mid_tag)::value;
+    const int8_t* st = lds + (ts % kStages32) * C::STAGE;
+    const int8_t* nst = lds + ((ts + 1) % kStages32) * C::STAGE;
+    v4i af[S];
+    af[0] = a0;
+#pragma unroll
+    for (int s = 1; s < S; ++s) af[s] = read_a(st, s);
+#pragma unroll
+    for (int u = C::HI; u < S; ++u)
+      acc[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[u], af[0], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < C::HI; ++u)
+      acc[u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[u], af[0], acc[u], 0, 0, 0);
+#pragma unroll
+    for (int s = 1; s < C::SPLIT; ++s) mult(s, af[s]);
+    sched_interleave<0x100, 1, S - 1>();  // one MFMA, one fragment read (0x008 MFMA, 0x100 DS read)
+    if constexpr (MID == 2) {
+      wait_vm_lgkm0<C::LOADS>();  // step ts + 1 has landed; ts + 2 may be in flight
+      bare_barrier();
+    } else if constexpr (MID == 1) {
+      if (ts + 2 < nsteps) wait_vm_lgkm0<C::LOADS>();
+      else wait_vm_lgkm0<0>();
+      bare_barrier();
+    }
+    if constexpr (MID != 0) {
+#pragma unroll
+      for (int u = C::HI; u < S; ++u) bf[u] = *reinterpret_cast<const v4i*>(nst + b_frag + 2 * u * kChunk);
+      a0 = read_a(nst, 0);
+    }
+    if constexpr (MID == 2) issue(ts + 3);
+#pragma unroll
+    for (int s = C::SPLIT; s < S; ++s) mult(s, af[s]);
+    if constexpr (MID != 0) {
+#pragma unroll
+      for (int u = C::HI - 1; u >= 0; --u)
+        bf[u] = *reinterpret_cast<const v4i*>(nst + b_frag + 2 * u * kChunk);
+    }
+    if constexpr (MID == 2) {
+      sched_group<0x100, C::SPLIT + 1>();                        // next B and A fragments
+      sched_interleave<0x020, 1, (C::LOADS < C::PART2 ? C::LOADS : C::PART2)>();  // MFMA, load
+    }
+    if (++since_fold == g.flush_steps) {
+      fold();
+      since_fold = 0;
+    }
+  };
+  int ts = 0;
+  for (; ts + 3 < nsteps; ++ts) step(std::integral_constant<int, 2>{}, ts);
+  for (; ts + 1 < nsteps; ++ts) step(std::integral_constant<int, 1>{}, ts);
+  step(std::integral_constant<int, 0>{}, ts);
+  if (since_fold) fold();
+
+  // Epilogue: C(i,j) := alpha * 2^(e_i + f_j) * C'(i,j) + beta * C(i,j).
+  const int64_t i = row0 + 32 * wave_m + (lane & 31);
+  if (i >= g.m) return;
+  const int ei = decode_exponent(g.ea[i]);
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t j = col0 + 32 * wave_n + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (j >= g.n) continue;
+    double* c = g.C + j * g.ldc + i;
+    const double v = alpha * ldexp(cf[r], ei + decode_exponent(g.eb[j]));
+    *c = (beta != 0.0) ? v + beta * *c : v;
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+split_gemm32_kernel(SplitArgs g, int tiles_m, int tiles_n) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kStages32 * Cfg32<S>::STAGE + kChunk];
+  split32_tile<S>(g, tiles_m, tiles_n, lds);
+}
+
 typedef void (*SliceFn)(const double*, int64_t, int64_t, int64_t, int64_t, int8_t*,
                         const int32_t*);
 typedef void (*GemmFn)(SplitArgs, int, int);
 
-template <int S>
-struct Entry {
-  static constexpr SliceFn rows = split_tile_kernel<S, true>;
-  static constexpr SliceFn cols = split_tile_kernel<S, false>;
-  static constexpr GemmFn gemm = split_gemm_kernel<S>;
-};
-
+// The GEMM kernel for S slices: the 32x32x32 kernel up to kMaxSlices32 (128x64 tiles, 32-deep
+// steps), the 16x16x64 kernel beyond (64x64 tiles, 64-deep steps).
 struct Fns {
   SliceFn rows, cols;
   GemmFn gemm;
+  int mt, nt, kstep;
 };
 
 const Fns kFns[kMaxSlices + 1] = {
-    {nullptr, nullptr, nullptr},
-    {Entry<1>::rows, Entry<1>::cols, Entry<1>::gemm},
-    {Entry<2>::rows, Entry<2>::cols, Entry<2>::gemm},
-    {Entry<3>::rows, Entry<3>::cols, Entry<3>::gemm},
-    {Entry<4>::rows, Entry<4>::cols, Entry<4>::gemm},
-    {Entry<5>::rows, Entry<5>::cols, Entry<5>::gemm},
-    {Entry<6>::rows, Entry<6>::cols, Entry<6>::gemm},
-    {Entry<7>::rows, Entry<7>::cols, Entry<7>::gemm},
-    {Entry<8>::rows, Entry<8>::cols, Entry<8>::gemm},
-    {Entry<9>::rows, Entry<9>::cols, Entry<9>::gemm},
-    {Entry<10>::rows, Entry<10>::cols, Entry<10>::gemm},
+    {nullptr, nullptr, nullptr, 0, 0, 0},
+    {split_tile_kernel<1, true>, split_tile_kernel<1, false>, split_gemm32_kernel<1>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<2, true>, split_tile_kernel<2, false>, split_gemm32_kernel<2>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<3, true>, split_tile_kernel<3, false>, split_gemm32_kernel<3>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<4, true>, split_tile_kernel<4, false>, split_gemm32_kernel<4>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<5, true>, split_tile_kernel<5, false>, split_gemm32_kernel<5>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<6, true>, split_tile_kernel<6, false>, split_gemm32_kernel<6>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<7, true>, split_tile_kernel<7, false>, split_gemm32_kernel<7>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<8, true>, split_tile_kernel<8, false>, split_gemm32_kernel<8>, kMT32, kNT32, kKStep32},
+    {split_tile_kernel<9, true>, split_tile_kernel<9, false>, split_gemm_kernel<9>, kTile, kTile, kKStep},
+    {split_tile_kernel<10, true>, split_tile_kernel<10, false>, split_gemm_kernel<10>, kTile, kTile, kKStep},
 };
+static_assert(kMaxSlices32 == 8 && kMaxSlices == 10, "the table above lists each slice count");
 
 bool is_notrans(char t) { return t == 'N' || t == 'n'; }
 bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
@@ -420,8 +673,8 @@ struct Layout {
 Layout layout(int64_t m, int64_t n, int64_t k, int S) {
   Layout L;
   L.kp = kpad(k);
-  L.a_bytes = align256((int64_t)S * round64(m) * L.kp);
-  L.b_bytes = align256((int64_t)S * round64(n) * L.kp);
+  L.a_bytes = align256((int64_t)S * round128(m) * L.kp);
+  L.b_bytes = align256((int64_t)S * round128(n) * L.kp);
   L.ea_off = L.a_bytes + L.b_bytes;
   L.eb_off = L.ea_off + align256(4 * m);
   L.total = L.eb_off + align256(4 * n);
@@ -441,10 +694,11 @@ int launch(const void* fn, dim3 grid, dim3 block, hipStream_t s, void** argv) {
 int launch_slices(const Fns& f, bool row_contig, const double* X, int64_t ld, int64_t rows,
                   int64_t k, int64_t kp, int8_t* out, int32_t* exps, hipStream_t s) {
   if (rows == 0) return MDG_SUCCESS;
-  const unsigned row_blocks = (unsigned)(round64(rows) / 64);
+  const unsigned max_blocks = (unsigned)(round64(rows) / 64);
+  const unsigned row_blocks = (unsigned)(round128(rows) / 64);
   if (k > 0) {
     void* argv[] = {&X, &ld, &rows, &k, &exps};
-    const dim3 grid(row_blocks, (unsigned)((k + kMaxChunk - 1) / kMaxChunk));
+    const dim3 grid(max_blocks, (unsigned)((k + kMaxChunk - 1) / kMaxChunk));
     const void* fn = row_contig ? reinterpret_cast<const void*>(&split_max_kernel<true>)
                                 : reinterpret_cast<const void*>(&split_max_kernel<false>);
     const int st = launch(fn, grid, dim3(256), s, argv);
@@ -527,7 +781,8 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return 15;
   if (L.a_bytes > (int64_t)0xFFFFFFFF - 4096 || L.b_bytes > (int64_t)0xFFFFFFFF - 4096)
     return MDG_ERR_SIZE;  // slice offsets are 32-bit
-  const int64_t tiles_m = (m + kTile - 1) / kTile, tiles_n = (n + kTile - 1) / kTile;
+  const Fns& f = kFns[nslices];
+  const int64_t tiles_m = (m + f.mt - 1) / f.mt, tiles_n = (n + f.nt - 1) / f.nt;
   if (tiles_m * tiles_n > (int64_t)INT32_MAX / 256) return MDG_ERR_SIZE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -536,7 +791,6 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   int8_t* bs = ws + L.a_bytes;
   int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
   int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
-  const Fns& f = kFns[nslices];
   // ea and eb are adjacent: zero both encoded exponent arrays in one launch
   int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), ea,
                        (L.total - L.ea_off) / 4, s);
@@ -546,16 +800,16 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   st = launch_slices(f, is_notrans(transb), B, ldb, n, k, L.kp, bs, eb, s);
   if (st) return st;
 
-  // INT32 headroom: a diagonal sums at most nslices products of 64 terms of magnitude <= 127^2
-  // per k-step.
-  const int64_t per_step = (int64_t)nslices * kKStep * kSliceMax * kSliceMax;
+  // INT32 headroom: a diagonal sums at most nslices products of f.kstep terms of magnitude
+  // <= 127^2 per k-step.
+  const int64_t per_step = (int64_t)nslices * f.kstep * kSliceMax * kSliceMax;
   int flush = (int)((int64_t)INT32_MAX / per_step);
   if (flush < 1) flush = 1;
   SplitArgs g{m, n, L.kp, alpha, beta, C, ldc, as, bs, ea, eb, flush};
   int tm = (int)tiles_m, tn = (int)tiles_n;
   void* argv[] = {&g, &tm, &tn};
   return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)((tiles_m * tiles_n + 7) / 8 * 8)),
-                dim3(kThreads), s, argv);
+                dim3(kThreads), s, argv);  // both GEMM kernels run kThreads threads
 }
 
 }  // extern "C"

@@ -57,6 +57,17 @@ def _storage_from_rows(rows_view, operand, trans, pad=5):
     return X, ld
 
 
+def _slice_byte_index(rp, kp):
+    """[r, p] -> byte offset of entry (r, p) within one slice, as the library header states."""
+    r = np.arange(rp, dtype=np.int64)[:, None]
+    p = np.arange(kp, dtype=np.int64)[None, :]
+    i, h = r % 32, (p // 16) % 2
+    slot = 2 * i + (h ^ (((i // 4) ^ (i // 8)) & 1))
+    idx = (p // 32) * rp * 32 + (r // 32) * 1024 + 16 * slot + p % 16
+    assert np.array_equal(np.sort(idx.ravel()), np.arange(rp * kp)), "layout is a permutation"
+    return idx
+
+
 @pytest.mark.parametrize("S", [1, 4, 7, 10])
 @pytest.mark.parametrize("operand,trans", [(0, "N"), (0, "T"), (1, "N"), (1, "T")])
 def test_slices_match_reference_bytewise(operand, trans, S):
@@ -69,15 +80,15 @@ def test_slices_match_reference_bytewise(operand, trans, S):
     rows_view[:, 3] = 0.0   # zero entries
     X, ld = _storage_from_rows(rows_view, operand, trans)
     kp = (k + 63) // 64 * 64
-    rp = (rows + 63) // 64 * 64
+    rp = (rows + 127) // 128 * 128
     want_q, want_e = oz.split_rows(rows_view, S)
     dX = torch.from_numpy(X).cuda()
     sl = torch.full((S * rp * kp,), 99, dtype=torch.int8, device="cuda")
     ex = torch.full((rows,), -999, dtype=torch.int32, device="cuda")
     assert mdg.mdg_split_slices(operand, trans, rows, k, dX, ld, S, sl, ex) == 0
     torch.cuda.synchronize()
-    # k-panel tiles [s][p // 64][r][p % 64] -> [s][r][p]
-    got = sl.cpu().numpy().reshape(S, kp // 64, rp, 64).transpose(0, 2, 1, 3).reshape(S, rp, kp)
+    idx = _slice_byte_index(rp, kp)
+    got = sl.cpu().numpy().reshape(S, rp * kp)[:, idx]
     assert np.array_equal(ex.cpu().numpy(), want_e.astype(np.int32))
     for s in range(S):
         assert np.array_equal(got[s, :rows, :k], want_q[s]), f"slice {s + 1}"
@@ -88,7 +99,7 @@ def test_slices_match_reference_bytewise(operand, trans, S):
 SHAPES = [(1, 1, 1), (17, 33, 5), (64, 64, 64), (65, 63, 130), (130, 70, 200), (200, 129, 64)]
 
 
-@pytest.mark.parametrize("S", [1, 3, 7, 8])
+@pytest.mark.parametrize("S", [1, 3, 7, 8, 9, 10])  # both GEMM kernels (up to 8 slices; beyond)
 @pytest.mark.parametrize("trans", TRANS)
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_slice_products_match_reference_bitwise(shape, trans, S):
@@ -122,10 +133,12 @@ def test_integer_inputs_are_exact(S):
     assert same_bits(logical(got, 150, 140, p["ldc"]), logical(ref, 150, 140, p["ldc"]))
 
 
-def test_int32_fold_path_long_k():
-    # S = 10: INT32 sums are folded into FP64 every 208 k-steps of 64; k = 14000 crosses a fold
-    p = synth.problem(34, 0, "N", "T", 80, 72, 14000, ld_rule=_pad3, dist="scaled", phi=32)
-    got = _run_split(p, 1.0, 1.0, 10)
+# INT32 sums are folded into FP64 before they could overflow: for 10 slices every 208 k-steps of
+# 64 (k = 13312), for 8 slices every 520 k-steps of 32 (k = 16640); each k below crosses a fold.
+@pytest.mark.parametrize("S,k,phi", [(10, 14000, 32), (8, 17000, 8)])
+def test_int32_fold_path_long_k(S, k, phi):
+    p = synth.problem(34, 0, "N", "T", 80, 72, k, ld_rule=_pad3, dist="scaled", phi=phi)
+    got = _run_split(p, 1.0, 1.0, S)
     ref, D = run_oracle(p, 1.0, 1.0)
     assert rel_err(logical(got, 80, 72, p["ldc"]).T, logical(ref, 80, 72, p["ldc"]).T, D) <= TOL
 

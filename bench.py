@@ -159,8 +159,6 @@ def split_workload(args, torch, mdg):
     import numpy as np
 
     import synth
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from gpu_util import rel_err, sample_indices, sampled_reference
     m = n = k = args.split_size
     results = []
     for phi, S in SPLIT_CASES:
@@ -195,18 +193,27 @@ def split_workload(args, torch, mdg):
             e1.record()
             torch.cuda.synchronize()
             times[name] = e0.elapsed_time(e1) / args.steps
-        # accuracy of one split call from the original C, on sampled full rows and columns
+        # Accuracy over the whole of C, on the GPU: one split call and one native call from the
+        # original C, and D = |A||B| + |C0| from a native call on absolute values. The native FP64
+        # result is within rounding (about 1e-16 D) of the exact one, so this bounds the split
+        # error against the exact product to that margin. (The test suite checks the same inputs
+        # against the CPU oracle.)
         dC.copy_(dC0)
         split_call()
-        torch.cuda.synchronize()
-        R = sample_indices(m, 6, synth.seed_for(3, phi, 5))
-        Sx = sample_indices(n, 6, synth.seed_for(3, phi, 6))
-        c2 = dC.view(n, p["ldc"])
-        gr = c2[:, torch.from_numpy(R).cuda()].T.cpu().numpy()
-        gc = c2[torch.from_numpy(Sx).cuda(), :m].T.cpu().numpy()
-        del dA, dB, dC, dC0, ws, c2
-        rr, dr, rc, dc = sampled_reference(p, 1.0, 1.0, R, Sx)
-        err = max(rel_err(gr, rr, dr), rel_err(gc, rc, dc))
+        c_split = dC.clone()
+        dC.copy_(dC0)
+        native_call()
+        dD = dC0.abs()
+        st = mdg.mdg_dgemm("N", "N", m, n, k, 1.0, dA.abs(), p["lda"], dB.abs(), p["ldb"], 1.0, dD,
+                           p["ldc"])
+        if st:
+            raise RuntimeError(mdg.mdg_status_string(st))
+        ld = p["ldc"]
+        diff = (c_split.view(n, ld)[:, :m] - dC.view(n, ld)[:, :m]).abs()
+        den = dD.view(n, ld)[:, :m]
+        ratio = torch.where(den > 0, diff / den, torch.where(diff > 0, float("inf"), 0.0))
+        err = float(ratio.max())
+        del dA, dB, dC, dC0, dD, ws, c_split, diff, den, ratio
         fl = 2.0 * m * n * k
         products = S * (S + 1) // 2
         results.append({
@@ -216,7 +223,7 @@ def split_workload(args, torch, mdg):
             "native_tflops": round(fl / (times["native"] * 1e-3) / 1e12, 2),
             "int8_tops_in_call": round(products * fl / (times["split"] * 1e-3) / 1e12, 1),
             "speedup_vs_native": round(times["native"] / times["split"], 3),
-            "max_err_vs_oracle": float(f"{err:.3g}"),
+            "max_err_vs_native_fp64": float(f"{err:.3g}"),
         })
         log(f"[bench] split phi={phi} S={S}: {results[-1]}")
     best = max(results, key=lambda r: r["split_tflops_equiv"])

@@ -38,6 +38,8 @@ def load_library(path: str):
     lib.oracle_dgemm_absden.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64,
                                         ctypes.c_double, dp, i64, dp, i64,
                                         ctypes.c_double, dp, i64, dp, i64]
+    lib.oracle_dgemm_dd.restype = ctypes.c_int
+    lib.oracle_dgemm_dd.argtypes = lib.oracle_dgemm.argtypes
     lib.oracle_set_threads.restype = None
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
@@ -75,6 +77,13 @@ def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lib=None
     """
     return (lib or _load()).oracle_dgemm(_ch(transa), _ch(transb), m, n, k, float(alpha),
                                 _ptr(A), lda, _ptr(B), ldb, float(beta), _ptr(C), ldc)
+
+
+def dgemm_dd(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, lib=None):
+    """As dgemm, each entry in doubled precision (Dot2) and rounded once: the true-error
+    reference, not the parity target."""
+    return (lib or _load()).oracle_dgemm_dd(_ch(transa), _ch(transb), m, n, k, float(alpha),
+                                   _ptr(A), lda, _ptr(B), ldb, float(beta), _ptr(C), ldc)
 
 
 def absden(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc, D, ldd, lib=None):

@@ -53,7 +53,20 @@ int oracle_dgemm_absden(char transa, char transb, int64_t m, int64_t n, int64_t 
                         double beta, const double *C0, int64_t ldc,
                         double *D, int64_t ldd);
 
-/* Number of OpenMP threads the two routines above use (<= 0 resets to the default). */
+/*
+ * The same operation with each entry evaluated in doubled working precision
+ * (error-free TwoProduct and TwoSum with the errors summed on the side, the Dot2
+ * algorithm of Ogita, Rump and Oishi, 2005) and rounded once at the end: within
+ * about one rounding of the exact result, so it states the true error of the
+ * routine above and of the GPU paths. Same arguments, checks and conventions as
+ * oracle_dgemm. Not a parity target.
+ */
+int oracle_dgemm_dd(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                    double alpha, const double *A, int64_t lda,
+                    const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc);
+
+/* Number of OpenMP threads the routines above use (<= 0 resets to the default). */
 void oracle_set_threads(int nthreads);
 int oracle_get_threads(void);
 

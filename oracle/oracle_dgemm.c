@@ -140,3 +140,70 @@ int oracle_dgemm_absden(char transa, char transb, int64_t m, int64_t n, int64_t 
     }
     return 0;
 }
+
+/*
+ * Extended-precision reference (not the parity target; it states the true error of
+ * the oracle above, of the native kernel and of the split path). Each entry is the
+ * same dot product evaluated with error-free transformations: the product of two
+ * doubles is h + r exactly (TwoProduct: h = fl(a*b), r = fma(a, b, -h)), the sum of
+ * two doubles is s + q exactly (TwoSum, Knuth), and the rounding errors r and q are
+ * summed on the side (Ogita, Rump and Oishi, "Accurate sum and dot product", SIAM J.
+ * Sci. Comput. 26(6), 2005, algorithm Dot2). The result is as accurate as a dot
+ * product computed in twice the working precision and then rounded:
+ * |s + c - x'y| <= u|x'y| + gamma_k^2 |x|'|y|. alpha and beta are applied to the
+ * pair (s, c) with the same transformations before the single final rounding.
+ */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double *h, double *r)
+{
+    double x = a * b;
+    *r = fma(a, b, -x);
+    *h = x;
+}
+
+int oracle_dgemm_dd(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                    double alpha, const double *A, int64_t lda,
+                    const double *B, int64_t ldb,
+                    double beta, double *C, int64_t ldc)
+{
+    int empty = (m == 0 || n == 0);
+    int no_product = (alpha == 0.0 || k == 0);
+    int info = check_args(transa, transb, m, n, k, A, lda, B, ldb, C, ldc,
+                          !empty && !no_product, !empty);
+    if (info) return info;
+    if (empty) return 0;
+    if (beta == 1.0 && no_product) return 0;
+
+    int ta = is_trans(transa), tb = is_trans(transb);
+    int nt = oracle_get_threads();
+
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            double s = 0.0, c = 0.0;
+            if (!no_product) {
+                for (int64_t p = 0; p < k; ++p) {
+                    double h, r, q;
+                    two_prod(op_a(ta, A, lda, i, p), op_b(tb, B, ldb, p, j), &h, &r);
+                    two_sum(s, h, &s, &q);
+                    c = c + (q + r);
+                }
+            }
+            /* alpha*(s + c) + beta*c0, rounded once at the end */
+            double t, tr, u = 0.0, ur = 0.0, v, vr;
+            two_prod(alpha, s, &t, &tr);
+            tr = tr + alpha * c;
+            if (beta != 0.0) two_prod(beta, C[j * ldc + i], &u, &ur);
+            two_sum(t, u, &v, &vr);
+            C[j * ldc + i] = v + (vr + (tr + ur));
+        }
+    }
+    return 0;
+}

@@ -29,6 +29,15 @@ What pins what:
   threads         bitwise independence of the OpenMP thread count
   validation      argument-check codes in argument order
   bruteforce      a pure-Python float loop on tiny shapes, bitwise
+  dd_rational     the doubled-precision reference (oracle_dgemm_dd) against exact
+                  rationals: within one rounding of the exact result plus
+                  gamma_k^2 * D (Ogita, Rump and Oishi 2005, the Dot2 bound)
+  dd_cancellation constructed cancellations where the plain loop returns 0 and
+                  the exact answer is a product's or a sum's rounding error
+                  (each error term of TwoProduct/TwoSum, and of alpha*s and
+                  beta*c0, is the whole answer in one case)
+  dd_integer      integer-valued inputs: the reference equals the plain loop
+                  bitwise (both exact)
 """
 from __future__ import annotations
 
@@ -379,6 +388,74 @@ def pin_bruteforce(lib=None):
         assert np.array_equal(_bits(C), _bits(ref)), f"pure-Python loop {ta}{tb} {m}x{n}x{k}"
 
 
+def _run_dd(lib, p, alpha, beta, C=None):
+    C = p["C"].copy() if C is None else C
+    info = oracle.dgemm_dd(p["transa"], p["transb"], p["m"], p["n"], p["k"], alpha,
+                           p["A"], p["lda"], p["B"], p["ldb"], beta, C, p["ldc"], lib=lib)
+    assert info == 0, f"oracle_dgemm_dd returned {info}"
+    return C
+
+
+def pin_dd_rational(lib=None):
+    shapes = [(1, 1, 1), (2, 3, 4), (4, 3, 9), (3, 2, 17)]
+    for (m, n, k), ta, tb in itertools.product(shapes, TRANS, TRANS):
+        alpha, beta = 0.7, -1.3
+        p = synth.problem(95, 0, ta, tb, m, n, k, ld_rule=_pad3)
+        C0 = synth.view2d(p["C"], m, n, p["ldc"]).copy()
+        got = synth.view2d(_run_dd(lib, p, alpha, beta), m, n, p["ldc"])
+        a = _op(p["A"], ta, m, k, p["lda"])
+        b = _op(p["B"], tb, k, n, p["ldb"])
+        for i in range(m):
+            for j in range(n):
+                s = sum(Fraction(a[i, q]) * Fraction(b[q, j]) for q in range(k))
+                exact = Fraction(alpha) * s + Fraction(beta) * Fraction(C0[i, j])
+                dex = abs(Fraction(alpha)) * sum(abs(Fraction(a[i, q]) * Fraction(b[q, j]))
+                                                 for q in range(k)) \
+                    + abs(Fraction(beta)) * abs(Fraction(C0[i, j]))
+                bound = Fraction(2 * U) * abs(exact) + Fraction(4 * _gamma(k + 2) ** 2) * dex
+                assert abs(Fraction(got[i, j]) - exact) <= bound, f"dd rational {ta}{tb} ({i},{j})"
+
+
+def _dot_case(lib, x, y, alpha=1.0, beta=0.0, c0=0.0):
+    """alpha * x'y + beta * c0 through the reference (m = n = 1, op = N)."""
+    k = len(x)
+    C = np.array([c0], dtype=np.float64)
+    info = oracle.dgemm_dd("N", "N", 1, 1, k, alpha, np.array(x, dtype=np.float64), 1,
+                           np.array(y, dtype=np.float64), max(1, k), beta, C, 1, lib=lib)
+    assert info == 0
+    return C[0]
+
+
+def pin_dd_cancellation(lib=None):
+    e = 2.0 ** -30
+    a = 1.0 + e                      # a * a = 1 + 2^-29 + 2^-60: its rounding error is 2^-60
+    aa = a * a                       # binary64 product (1 + 2^-29)
+    assert float(Fraction(a) * Fraction(a) - Fraction(aa)) == 2.0 ** -60
+    # a sum's rounding error is the answer: 2^60 + 1.5 rounds to 2^60
+    assert _dot_case(lib, [2.0 ** 60, 1.5, -(2.0 ** 60)], [1.0, 1.0, 1.0]) == 1.5, "TwoSum error"
+    # a product's rounding error is the answer: a*a - fl(a*a)
+    assert _dot_case(lib, [a, -1.0], [a, aa]) == 2.0 ** -60, "TwoProduct error"
+    # alpha * s has a rounding error that beta * c0 cancels down to
+    assert _dot_case(lib, [a], [1.0], alpha=a, beta=-1.0, c0=aa) == 2.0 ** -60, "alpha*s error"
+    # beta * c0 has the rounding error
+    assert _dot_case(lib, [aa], [1.0], alpha=-1.0, beta=a, c0=a) == 2.0 ** -60, "beta*c0 error"
+    # and the plain loop indeed returns 0 on the first two (what the reference is for)
+    C = np.array([0.0])
+    oracle.dgemm("N", "N", 1, 1, 3, 1.0, np.array([2.0 ** 60, 1.5, -(2.0 ** 60)]), 1,
+                 np.ones(3), 3, 0.0, C, 1, lib=lib)
+    assert C[0] == 0.0
+
+
+def pin_dd_integer(lib=None):
+    for ta, tb in itertools.product(TRANS, TRANS):
+        p = synth.problem(96, 0, ta, tb, 13, 11, 29, ld_rule=_pad3, dist="int")
+        plain = _run(lib, p, 1.5, 0.5)
+        dd = _run_dd(lib, p, 1.5, 0.5)
+        assert np.array_equal(_bits(plain), _bits(dd)), f"dd integer {ta}{tb}"
+        _pad_rows_untouched(p, dd)
+
+
 ALL_PINS = [pin_golden_ld, pin_ones, pin_identity, pin_permutation, pin_integer_exact,
             pin_rational, pin_library_matmul, pin_transpose, pin_zero_rules, pin_nan_row,
-            pin_threads, pin_validation, pin_bruteforce]
+            pin_threads, pin_validation, pin_bruteforce, pin_dd_rational, pin_dd_cancellation,
+            pin_dd_integer]

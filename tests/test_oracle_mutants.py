@@ -64,6 +64,14 @@ MUTANTS = {
                            "s = s + op_a(ta, A, lda, i, p) * fabs(op_b(tb, B, ldb, p, j));"),
     "quick_return_any_beta": ("if (no_product && beta == 1.0) return 0;",
                               "if (no_product) return 0;"),
+    "dd_product_error_dropped": ("*r = fma(a, b, -x);", "*r = 0.0 * fma(a, b, -x);"),
+    "dd_sum_error_dropped": ("c = c + (q + r);", "c = c + r;"),
+    "dd_twosum_sign": ("*e = (a - (x - z)) + (b - z);", "*e = (a - (x - z)) - (b - z);"),
+    "dd_alpha_low_dropped": ("tr = tr + alpha * c;", "tr = alpha * c;"),
+    "dd_beta_low_dropped": ("C[j * ldc + i] = v + (vr + (tr + ur));",
+                            "C[j * ldc + i] = v + (vr + tr);"),
+    "dd_op_b_first_only": ("two_prod(op_a(ta, A, lda, i, p), op_b(tb, B, ldb, p, j), &h, &r);",
+                           "two_prod(op_a(ta, A, lda, i, p), op_b(tb, B, ldb, 0, j), &h, &r);"),
 }
 
 

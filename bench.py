@@ -107,18 +107,20 @@ def run_step(mdg, probs, events=None, variant=-1):
             events[i][1].record()
 
 
-def cpu_baseline(probs, budget_s: float):
+def cpu_baseline(probs, budget_s: float, threads: int = 0):
     """Time the CPU oracle on blocks of the sweep problems, on the host copies of the inputs.
 
     Each problem gets an equal share of the budget. Within it the oracle computes
     consecutive r x c blocks of C (c = one column per thread, r starting at 16 rows and
     doubling while a call takes under a quarter of the share), walking down the leading
     columns, on the problem's own arrays with pointer offsets (no data movement; the
-    results go to a scratch C). Returns (TFLOP/s, threads, description).
+    results go to a scratch C). threads = 0 uses every host thread OpenMP offers.
+    Returns (TFLOP/s, threads, description).
     """
     import numpy as np
 
     import oracle
+    oracle.set_threads(threads)
     threads = oracle.get_threads()
     share = budget_s / len(probs)
     total_flops, total_t, entries = 0.0, 0.0, 0
@@ -145,6 +147,7 @@ def cpu_baseline(probs, budget_s: float):
                 i0, j0 = 0, j0 + c
             if dt < share / 4:
                 r *= 2
+    oracle.set_threads(0)
     desc = (f"oracle on leading blocks of C of each of the {len(probs)} sweep GEMMs "
             f"({entries} entries of C, {total_t:.1f} s, one column per thread per call)")
     return total_flops / total_t / 1e12, threads, desc
@@ -505,7 +508,9 @@ def main():
     if args.cpu_budget > 0:
         log("[bench] timing the CPU oracle baseline")
         v, cores, desc = cpu_baseline(probs, args.cpu_budget)
-        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc}
+        v1, _, desc1 = cpu_baseline(probs, args.cpu_budget / 3, threads=1)
+        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc,
+               "value_1_thread": v1, "sample_1_thread": desc1}
 
     out = {
         "metric": METRIC,

@@ -128,3 +128,22 @@ def test_leading_dimension_offset_guard_is_host_side_and_exact():
     # alpha = 0: A and B are not read, so their leading dimensions do not matter
     st = mdg.mdg_dgemm("T", "N", 300, 64, 64, 0.0, fake, big, fake, 64, 1.0, fake, 300)
     assert st == 0  # quick return (beta = 1)
+
+
+def test_sweep_variant_choice():
+    """The measured choice for the sweep shapes (each a variant whose efficiency was measured on the
+    GPU for that transpose case): 256x128 ring tiles from 4096 up, smaller ring tiles for 1024 to
+    4099, the register-staged 128x64 tile for the HBM-bound k = 64 case."""
+    def name(ta, tb, m, n, k):
+        return mdg.mdg_variant_name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
+    for size in (4096, 8192, 16384):
+        for ta in "NT":
+            for tb in "NT":
+                want = "ring_f64_256x128x16_w64x64_s3_il" if ta == "T" else \
+                    "ring_f64_256x128x16_w64x32_s3_il"
+                assert name(ta, tb, size, size, size) == want
+    for ta in "NT":
+        for tb in "NT":
+            assert name(ta, tb, 1024, 1024, 1024).startswith("ring_f64_64x64x16")
+            assert name(ta, tb, 2048, 2048, 2048).startswith("ring_f64_128x")
+            assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"

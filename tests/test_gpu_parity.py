@@ -146,3 +146,45 @@ def test_runs_on_a_side_stream():
     s.synchronize()
     ref, _ = run_oracle(p, 1.0, 1.0)
     assert same_bits(logical(dC.cpu().numpy(), 257, 129, p["ldc"]), logical(ref, 257, 129, p["ldc"]))
+
+
+def test_concurrent_host_threads_on_separate_streams():
+    """The library is reentrant: four host threads, each with its own stream and problems, call
+    mdg_dgemm at the same time; every result matches the oracle bitwise (integer data)."""
+    import threading
+
+    import paper_1609_00076_amd as mdg
+    import torch
+    shapes = [(300, 200, 150), (129, 257, 64), (64, 64, 300), (500, 70, 33)]
+    probs = [synth.problem(17, i, "NT"[i % 2], "TN"[i // 2 % 2], m, n, k, ld_rule=_pad3, dist="int")
+             for i, (m, n, k) in enumerate(shapes)]
+    dev = [tuple(torch.from_numpy(p[x]).cuda() for x in "ABC") for p in probs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in probs]
+    status = [None] * len(probs)
+    barrier = threading.Barrier(len(probs))
+
+    def work(i):
+        p, (dA, dB, dC) = probs[i], dev[i]
+        barrier.wait()
+        sts = []
+        for _ in range(3):  # C := 1.0*op(A)op(B) + 0.5*C, three times on the same stream
+            sts.append(mdg.mdg_dgemm(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, dA,
+                                     p["lda"], dB, p["ldb"], 0.5, dC, p["ldc"], stream=streams[i]))
+        status[i] = sts
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for s in streams:
+        s.synchronize()
+    for i, p in enumerate(probs):
+        assert status[i] == [0, 0, 0], status[i]
+        ref = p["C"].copy()
+        for _ in range(3):
+            r, _ = run_oracle(p, 1.0, 0.5, C=ref)
+            ref = r
+        m, n = p["m"], p["n"]
+        assert same_bits(logical(dev[i][2].cpu().numpy(), m, n, p["ldc"]), logical(ref, m, n, p["ldc"]))

@@ -743,6 +743,7 @@ using Ring256wi = RingCfg<256, 128, 64, 64, 3, 2, 1>;   // 8 waves of 64x64, int
 using Ring64s3 = RingCfg<64, 64, 32, 32, 3, 3, 1>;      // 4 waves of 32x32, 3 stages, 3 WGs per CU
 using Ring64s4 = RingCfg<64, 64, 32, 32, 4, 2, 1>;      // 4 stages, 2 WGs per CU
 using Ring128x64 = RingCfg<128, 64, 32, 32, 3, 4, 1>;   // 8 waves of 32x32, 3 stages, 2 WGs per CU
+using Ring128x256wi = RingCfg<128, 256, 64, 64, 3, 2, 1>;  // 8 waves of 64x64 on a wide tile, 3 stages
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -827,6 +828,7 @@ const Variant kVariants[] = {
     make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811), 393),
     make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
     make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868), 400),
+    make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(941, 909, 941, 946)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

@@ -132,16 +132,16 @@ def test_leading_dimension_offset_guard_is_host_side_and_exact():
 
 def test_sweep_variant_choice():
     """The measured choice for the sweep shapes (each a variant whose efficiency was measured on the
-    GPU for that transpose case): 256x128 ring tiles from 4096 up, smaller ring tiles for 1024 to
-    4099, the register-staged 128x64 tile for the HBM-bound k = 64 case."""
+    GPU for that transpose case): 256x128 or 128x256 ring tiles from 4096 up, smaller ring tiles for
+    1024 to 4099, the register-staged 128x64 tile for the HBM-bound k = 64 case."""
     def name(ta, tb, m, n, k):
         return mdg.mdg_variant_name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
+    want = {"NN": "ring_f64_128x256x16_w64x64_s3_il", "NT": "ring_f64_256x128x16_w64x32_s3_il",
+            "TN": "ring_f64_256x128x16_w64x64_s3_il", "TT": "ring_f64_128x256x16_w64x64_s3_il"}
     for size in (4096, 8192, 16384):
         for ta in "NT":
             for tb in "NT":
-                want = "ring_f64_256x128x16_w64x64_s3_il" if ta == "T" else \
-                    "ring_f64_256x128x16_w64x32_s3_il"
-                assert name(ta, tb, size, size, size) == want
+                assert name(ta, tb, size, size, size) == want[ta + tb]
     for ta in "NT":
         for tb in "NT":
             assert name(ta, tb, 1024, 1024, 1024).startswith("ring_f64_64x64x16")

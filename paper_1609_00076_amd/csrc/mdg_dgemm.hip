@@ -744,6 +744,8 @@ using Ring64s3 = RingCfg<64, 64, 32, 32, 3, 3, 1>;      // 4 waves of 32x32, 3 s
 using Ring64s4 = RingCfg<64, 64, 32, 32, 4, 2, 1>;      // 4 stages, 2 WGs per CU
 using Ring128x64 = RingCfg<128, 64, 32, 32, 3, 4, 1>;   // 8 waves of 32x32, 3 stages, 2 WGs per CU
 using Ring128x256wi = RingCfg<128, 256, 64, 64, 3, 2, 1>;  // 8 waves of 64x64 on a wide tile, 3 stages
+using Ring256x128t = RingCfg<256, 128, 128, 32, 3, 2, 1>;  // 8 waves of 128x32, 3 stages
+using Ring128x256t = RingCfg<128, 256, 128, 32, 3, 2, 1>;  // 8 waves of 128x32 on a wide tile
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -829,6 +831,8 @@ const Variant kVariants[] = {
     make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
     make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868), 400),
     make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(941, 909, 941, 946)),
+    make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(940, 921, 948, 941)),
+    make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(950, 905, 943, 940)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

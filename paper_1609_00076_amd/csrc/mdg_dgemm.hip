@@ -561,38 +561,54 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
 
   // Fragment addresses (doubles from the stage base) of this lane for pair 0; pair h adds h * 8
   // k-rows (k-major) or flips slot bit 2 (row-major: slot (4h + c) ^ f = (4h) ^ (c ^ f)).
+  // Row-major: lane l16 feeds row ai + 16b of block b, and one 16-byte read gives it the k-values
+  // of both k-steps e of the pair.
+  // k-major: one 16-byte read gives lane l16 rows 2*l16 and 2*l16 + 1 of a 32-row group at one
+  // k-row (2*lq + 8h + e), which feed k-step e of two MFMA blocks: block 2p holds the group's even
+  // rows, block 2p + 1 its odd rows (the epilogue maps them back). In a 64-row tile, k-rows
+  // 2*lq + 8h + e all have bit 1 equal to lq & 1, so kmaj_index flips bit 4 of the row for odd lq
+  // (the wave's rows start at a multiple of 32): the pair moves to (2*l16) ^ 16.
   const int ai = wave_m * R::WM + l16, bj = wave_n * R::WN + l16;
-  // k-major: this lane's k-row 2*lq (+ 8h + e) and row ai (bj) of block 0. Block b adds 16 rows;
-  // in a 64-row tile k-rows 2*lq + 8h + e all have bit 1 equal to lq & 1, so kmaj_index flips
-  // bit 4 of the row for odd lq (the wave's rows start at a multiple of 32, so bit 4 of
-  // ai + 16b is the block's parity): block b is read at 16 * (b ^ (lq & 1)).
-  const int a_kmaj = 2 * lq * R::ROW_A + ai;
-  const int b_kmaj = R::STAGE_A + 2 * lq * R::ROW_B + bj;
   const int kflip = lq & 1;
   static_assert(R::MT != 64 || R::WM % 32 == 0, "64-row tiles: wave rows start at multiples of 32");
   static_assert(R::NT != 64 || R::WN % 32 == 0, "64-row tiles: wave rows start at multiples of 32");
+  static_assert(R::BM % 2 == 0 && R::BN % 2 == 0, "k-major reads feed blocks in pairs");
   const int a_rmaj = ai * R::KT + 2 * (lq ^ ring_swz(l16));
   const int b_rmaj = R::STAGE_A + bj * R::KT + 2 * (lq ^ ring_swz(l16));
+  const int a_kp = 2 * lq * R::ROW_A + wave_m * R::WM +
+                   (R::MT == 64 ? ((2 * l16) ^ (16 * kflip)) : 2 * l16);
+  const int b_kp = R::STAGE_A + 2 * lq * R::ROW_B + wave_n * R::WN +
+                   (R::NT == 64 ? ((2 * l16) ^ (16 * kflip)) : 2 * l16);
 
   typedef double d2 __attribute__((ext_vector_type(2)));
   auto read_frags = [&](const double* st, int h, d2 (&fa)[R::BM], d2 (&fb)[R::BN]) {
+    if constexpr (!TA) {
 #pragma unroll
-    for (int b = 0; b < R::BM; ++b) {
-      if (!TA) {
-        const double* p = st + a_kmaj + 8 * h * R::ROW_A + 16 * (R::MT == 64 ? (b ^ kflip) : b);
-        fa[b] = (d2){p[0], p[R::ROW_A]};
-      } else {
+      for (int p = 0; p < R::BM / 2; ++p) {
+        const double* q = st + a_kp + 8 * h * R::ROW_A + 32 * p;
+        const d2 t0 = *reinterpret_cast<const d2*>(q);
+        const d2 t1 = *reinterpret_cast<const d2*>(q + R::ROW_A);
+        fa[2 * p] = (d2){t0[0], t1[0]};
+        fa[2 * p + 1] = (d2){t0[1], t1[1]};
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < R::BM; ++b)
         fa[b] = *reinterpret_cast<const d2*>(st + ((a_rmaj + 16 * b * R::KT) ^ (8 * h)));
-      }
     }
+    if constexpr (TB) {
 #pragma unroll
-    for (int b = 0; b < R::BN; ++b) {
-      if (TB) {
-        const double* p = st + b_kmaj + 8 * h * R::ROW_B + 16 * (R::NT == 64 ? (b ^ kflip) : b);
-        fb[b] = (d2){p[0], p[R::ROW_B]};
-      } else {
-        fb[b] = *reinterpret_cast<const d2*>(st + ((b_rmaj + 16 * b * R::KT) ^ (8 * h)));
+      for (int p = 0; p < R::BN / 2; ++p) {
+        const double* q = st + b_kp + 8 * h * R::ROW_B + 32 * p;
+        const d2 t0 = *reinterpret_cast<const d2*>(q);
+        const d2 t1 = *reinterpret_cast<const d2*>(q + R::ROW_B);
+        fb[2 * p] = (d2){t0[0], t1[0]};
+        fb[2 * p + 1] = (d2){t0[1], t1[1]};
       }
+    } else {
+#pragma unroll
+      for (int b = 0; b < R::BN; ++b)
+        fb[b] = *reinterpret_cast<const d2*>(st + ((b_rmaj + 16 * b * R::KT) ^ (8 * h)));
     }
   };
 
@@ -626,8 +642,8 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     }
     d2 fa0[R::BM], fb0[R::BN], fa1[R::BM], fb1[R::BN];
     read_frags(smem, 0, fa0, fb0);
-    // Fragment reads per read_frags: one per block (16-byte row-major reads, or two 8-byte k-major
-    // reads the compiler pairs up).
+    // 16-byte fragment reads per read_frags: one per block (row-major), two per pair of blocks
+    // (k-major).
     constexpr int kReads = R::BM + R::BN;
     int t = 0;
     // Steady state: every iteration issues a full panel of loads and the panel read after its
@@ -675,32 +691,42 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     mfma_pair(fa1, fb1);
   }
 
-  // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
-  const int64_t i0 = row0 + ai, j0 = col0 + wave_n * R::WN + lq;
-  double* const cbase = g.C + j0 * g.ldc + i0;
+  // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read. Block bi
+  // holds rows 16*bi + l16 of the wave's rows (row-major op(A)) or, read in row pairs, rows
+  // 32*(bi/2) + 2*l16 + bi%2 (k-major op(A)); columns likewise with lq + 4r in place of l16.
   const double alpha = g.alpha, beta = g.beta;
+  auto row_of = [&](int bi) -> int64_t {
+    return row0 + wave_m * R::WM + (TA ? 16 * bi + l16 : 32 * (bi >> 1) + 2 * l16 + (bi & 1));
+  };
+  auto col_of = [&](int bj2, int r) -> int64_t {
+    return col0 + wave_n * R::WN +
+           (TB ? 32 * (bj2 >> 1) + 2 * (lq + 4 * r) + (bj2 & 1) : 16 * bj2 + lq + 4 * r);
+  };
 #pragma unroll
   for (int bj2 = 0; bj2 < R::BN; ++bj2) {
     double cb[R::BM][4];
     if (beta != 0.0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t dj = 16 * bj2 + 4 * r;
-        const bool col_ok = j0 + dj < g.n;
+        const int64_t j = col_of(bj2, r);
+        const bool col_ok = j < g.n;
 #pragma unroll
-        for (int bi = 0; bi < R::BM; ++bi)
-          cb[bi][r] = (col_ok && i0 + 16 * bi < g.m) ? cbase[dj * g.ldc + 16 * bi] : 0.0;
+        for (int bi = 0; bi < R::BM; ++bi) {
+          const int64_t i = row_of(bi);
+          cb[bi][r] = (col_ok && i < g.m) ? g.C[j * g.ldc + i] : 0.0;
+        }
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t dj = 16 * bj2 + 4 * r;
-      if (j0 + dj >= g.n) continue;
+      const int64_t j = col_of(bj2, r);
+      if (j >= g.n) continue;
 #pragma unroll
       for (int bi = 0; bi < R::BM; ++bi) {
-        if (i0 + 16 * bi < g.m) {
+        const int64_t i = row_of(bi);
+        if (i < g.m) {
           const double v = alpha * acc[bi][bj2][r];
-          cbase[dj * g.ldc + 16 * bi] = (beta != 0.0) ? v + beta * cb[bi][r] : v;
+          g.C[j * g.ldc + i] = (beta != 0.0) ? v + beta * cb[bi][r] : v;
         }
       }
     }
@@ -823,16 +849,16 @@ const Variant kVariants[] = {
     make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 0),
     make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
     make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
-    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(932, 924, 926, 931)),
+    make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(932, 941, 927, 925)),
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
-    make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(917, 923, 942, 941)),
+    make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(915, 940, 940, 948)),
     make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811), 393),
     make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
     make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868), 400),
-    make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(941, 909, 941, 946)),
-    make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(940, 921, 948, 941)),
-    make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(950, 905, 943, 940)),
+    make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(936, 947, 940, 946)),
+    make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(935, 939, 946, 945)),
+    make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

@@ -136,8 +136,8 @@ def test_sweep_variant_choice():
     1024 to 4099, the register-staged 128x64 tile for the HBM-bound k = 64 case."""
     def name(ta, tb, m, n, k):
         return mdg.mdg_variant_name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
-    want = {"NN": "ring_f64_128x256x16_w128x32_s3_il", "NT": "ring_f64_256x128x16_w64x32_s3_il",
-            "TN": "ring_f64_256x128x16_w128x32_s3_il", "TT": "ring_f64_128x256x16_w64x64_s3_il"}
+    want = {"NN": "ring_f64_128x256x16_w128x32_s3_il", "NT": "ring_f64_128x256x16_w64x64_s3_il",
+            "TN": "ring_f64_256x128x16_w128x32_s3_il", "TT": "ring_f64_256x128x16_w64x64_s3_il"}
     for size in (4096, 8192, 16384):
         for ta in "NT":
             for tb in "NT":

@@ -850,12 +850,12 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
     make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
     make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(932, 941, 927, 925)),
-    make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", 891),
+    make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", Eff(889, 902, 896, 896)),
     make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
     make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(915, 940, 940, 948)),
-    make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(816, 816, 816, 811), 393),
-    make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(808, 795, 787, 805)),
-    make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(861, 868, 869, 868), 400),
+    make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(827, 855, 836, 834), 393),
+    make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(804, 821, 827, 797)),
+    make_ring_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il", Eff(875, 905, 891, 875), 400),
     make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(936, 947, 940, 946)),
     make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(935, 939, 946, 945)),
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),

@@ -405,8 +405,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print("bench.py: measures one GPU only; --gpus must be 1 (the library has no "
+              "multi-GPU path: a GEMM would shard by output tiles, each GPU running this kernel)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -188,3 +188,29 @@ def test_concurrent_host_threads_on_separate_streams():
             ref = r
         m, n = p["m"], p["n"]
         assert same_bits(logical(dev[i][2].cpu().numpy(), m, n, p["ldc"]), logical(ref, m, n, p["ldc"]))
+
+
+@pytest.mark.parametrize("variant", VARIANTS[1:])
+def test_transposed_problem_gives_transposed_result_bitwise(variant):
+    """C^T = op(B)^T op(A)^T: dgemm(T, T, n, m, k, B, A) on the same storage returns C^T bit for
+    bit on Uniform[-1,1] data, for every kernel variant (each variant's k-order does not depend on
+    the transpose flags, and the products are the same numbers)."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    m, n, k = 200, 300, 517
+    p = synth.problem(18, 0, "N", "N", m, n, k, ld_rule=_pad3)
+    dA, dB = torch.from_numpy(p["A"]).cuda(), torch.from_numpy(p["B"]).cuda()
+    C0 = logical(p["C"], m, n, p["ldc"]).copy()          # m x n
+    c1 = torch.from_numpy(p["C"].copy()).cuda()
+    ldt = n + 3
+    ct = np.full(ldt * m, np.nan)
+    ct.reshape(m, ldt)[:, :n] = C0                       # C0^T stored column-major, n x m
+    c2 = torch.from_numpy(ct).cuda()
+    assert mdg.mdg_dgemm_ex(variant, "N", "N", m, n, k, 0.75, dA, p["lda"], dB, p["ldb"], -1.25, c1,
+                            p["ldc"]) == 0
+    assert mdg.mdg_dgemm_ex(variant, "T", "T", n, m, k, 0.75, dB, p["ldb"], dA, p["lda"], -1.25, c2,
+                            ldt) == 0
+    torch.cuda.synchronize()
+    r1 = logical(c1.cpu().numpy(), m, n, p["ldc"])
+    r2 = c2.cpu().numpy().reshape(m, ldt)[:, :n]
+    assert same_bits(r1, r2), f"variant {variant}"

@@ -214,3 +214,19 @@ def test_transposed_problem_gives_transposed_result_bitwise(variant):
     r1 = logical(c1.cpu().numpy(), m, n, p["ldc"])
     r2 = c2.cpu().numpy().reshape(m, ldt)[:, :n]
     assert same_bits(r1, r2), f"variant {variant}"
+
+
+@pytest.mark.parametrize("family", ["ring_", "mfma_"])
+@pytest.mark.parametrize("trans", TRANS)
+def test_variant_family_agrees_bitwise_on_float_data(trans, family):
+    """Within a kernel family every variant sums each entry's products in the same k-order (ring
+    kernels: 16-deep panels in order, k-index 8h + 2c + e within a panel; register-staged kernels:
+    4-deep MFMA steps in order), whatever the tile, wave layout or fragment read; so on
+    Uniform[-1,1] data all variants of a family return the same bits."""
+    import paper_1609_00076_amd as mdg
+    members = [v for v in VARIANTS[1:] if mdg.mdg_variant_name(v).startswith(family)]
+    assert len(members) >= 2
+    p = synth.problem(19, 0, trans[0], trans[1], 333, 277, 301, ld_rule=_pad3)
+    outs = [run_mdg(p, 0.5, 1.5, v) for v in members]
+    for v, o in zip(members[1:], outs[1:]):
+        assert same_bits(o, outs[0]), f"{mdg.mdg_variant_name(v)} vs {mdg.mdg_variant_name(members[0])}"

@@ -230,3 +230,50 @@ def test_variant_family_agrees_bitwise_on_float_data(trans, family):
     outs = [run_mdg(p, 0.5, 1.5, v) for v in members]
     for v, o in zip(members[1:], outs[1:]):
         assert same_bits(o, outs[0]), f"{mdg.mdg_variant_name(v)} vs {mdg.mdg_variant_name(members[0])}"
+
+
+def oracle_dgemm_dense(a, b, c, alpha, beta):
+    """c := alpha * a @ b + beta * c through the oracle (a, b, c dense 2-D arrays, updated in place)."""
+    import oracle
+    m, k = a.shape
+    n = b.shape[1]
+    A, B = np.ascontiguousarray(a.T).ravel(), np.ascontiguousarray(b.T).ravel()
+    C = np.ascontiguousarray(c.T).ravel()
+    st = oracle.dgemm("N", "N", m, n, k, alpha, A, m, B, k, beta, C, m)
+    c[:, :] = C.reshape(n, m).T
+    return st == 0
+
+
+def test_leading_dimensions_at_the_offset_limit():
+    """Leading dimensions just inside what the kernels' 32-bit panel offsets address: a 16-deep
+    k-panel of an operand strided along k spans 15 * ld + 256 elements, just under 4 GiB of bytes.
+    Every variant computes the GEMM exactly (integer data, NaN in every element outside the
+    matrices), for op(A) and for op(B) strided along k; a slightly larger ld is refused on the host."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    m, n, k = 70, 50, 40
+    ld = (((1 << 32) - 16) // 8 - 256) // 15            # 15 * ld + 256 elements fit 32-bit byte offsets
+    assert (15 * ld + 256) * 8 + 16 <= (1 << 32) < (15 * (ld + 20) + 256) * 8 + 16
+    g = synth.rng(synth.seed_for(20, 0, 0))
+    a = g.integers(-8, 9, (m, k)).astype(np.float64)     # op(A), m x k
+    b = g.integers(-8, 9, (k, n)).astype(np.float64)     # op(B), k x n
+    c0 = g.integers(-8, 9, (m, n)).astype(np.float64)
+    want = c0.copy()
+    assert oracle_dgemm_dense(a, b, want, 1.5, 0.5)
+    dA = torch.full((k * ld,), float("nan"), dtype=torch.float64, device="cuda")
+    dA.view(k, ld)[:, :m] = torch.from_numpy(a.T.copy()).cuda()          # A stored m x k, lda = ld
+    dBt = torch.full((k * ld,), float("nan"), dtype=torch.float64, device="cuda")
+    dBt.view(k, ld)[:, :n] = torch.from_numpy(b.copy()).cuda()           # B stored n x k, ldb = ld
+    dA_small = torch.from_numpy(a.T.copy().ravel()).cuda()               # A stored m x k, lda = m
+    dB_small = torch.from_numpy(b.T.copy().ravel()).cuda()               # B stored k x n, ldb = k
+    for v in VARIANTS:
+        for tb, B, ldb, A, lda in (("N", dB_small, k, dA, ld), ("T", dBt, ld, dA_small, m)):
+            dC = torch.from_numpy(c0.T.copy().ravel()).cuda()
+            st = mdg.mdg_dgemm_ex(v, "N", tb, m, n, k, 1.5, A, lda, B, ldb, 0.5, dC, m)
+            assert st == 0, (v, tb, mdg.mdg_status_string(st))
+            torch.cuda.synchronize()
+            got = dC.cpu().numpy().reshape(n, m).T
+            assert same_bits(got, want), f"variant {v} transb {tb}"
+    big = [v for v in VARIANTS[1:] if mdg.mdg_variant_name(v) == "ring_f64_256x128x16_w128x32_s3_il"][0]
+    dC = torch.from_numpy(c0.T.copy().ravel()).cuda()
+    assert mdg.mdg_dgemm_ex(big, "N", "N", m, n, k, 1.5, dA, ld + 20, dB_small, k, 0.5, dC, m) == -4

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = [os.path.join(HERE, "oracle_dgemm.c")]
+SOURCES = [os.path.join(HERE, "oracle_dgemm.c"), os.path.join(HERE, "oracle_blas3.c")]
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
           "-ffp-contract=off", "-fno-fast-math", "-fno-unsafe-math-optimizations",
@@ -14,7 +14,7 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
 
 
 def build(out: str = LIB_PATH, extra_flags=(), sources=None) -> str:
-    """Compile oracle_dgemm.c into a shared library; returns its path."""
+    """Compile the oracle sources into a shared library; returns its path."""
     tmp = out + ".tmp"
     cmd = ["gcc", *CFLAGS, *extra_flags, "-o", tmp, *(sources or SOURCES), "-lm"]
     subprocess.run(cmd, check=True)

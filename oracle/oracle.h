@@ -66,6 +66,17 @@ int oracle_dgemm_dd(char transa, char transb, int64_t m, int64_t n, int64_t k,
                     const double *B, int64_t ldb,
                     double beta, double *C, int64_t ldc);
 
+/* Level-3 BLAS built on the same definitions (oracle_blas3.c): symmetric rank-k
+   update, triangular multiply, triangular solve. Arguments in level-3 BLAS order;
+   each returns 0 or the 1-based position of the first bad argument (dtrmm: -1 if
+   its temporary cannot be allocated). */
+int oracle_dsyrk(char uplo, char trans, int64_t n, int64_t k, double alpha,
+                 const double *A, int64_t lda, double beta, double *C, int64_t ldc);
+int oracle_dtrmm(char side, char uplo, char transa, char diag, int64_t m, int64_t n,
+                 double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+int oracle_dtrsm(char side, char uplo, char transa, char diag, int64_t m, int64_t n,
+                 double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+
 /* Number of OpenMP threads the routines above use (<= 0 resets to the default). */
 void oracle_set_threads(int nthreads);
 int oracle_get_threads(void);

@@ -224,6 +224,77 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc *descs, const int32_t *tile_
  */
 int mdg_dgemm_grouped(const void *device_plan, int64_t num_tiles, int grid, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Level-3 operations built on the GEMM (the paper's Step 2, "Poorman's BLAS": with a fast GEMM
+ * on submatrices the other level-3 BLAS follow; Kagstrom, Ling and Van Loan). Definitions,
+ * argument order and argument checks are those of the level-3 BLAS routines of the same names
+ * (Dongarra, Du Croz, Hammarling and Duff, cited in the paper's section 1.1). Storage is
+ * column-major with leading dimensions, as above; device pointers, caller-owned, no workspace,
+ * asynchronous on `stream`. Return values as for mdg_dgemm: 0, the 1-based position of the first
+ * bad argument, or a negative MDG_ERR_* code.
+ * ------------------------------------------------------------------------------------------ */
+
+/*
+ * Symmetric rank-k update on one triangle of the n x n C:
+ *
+ *     C := alpha * op(A) * op(A)^T + beta * C,   op(A) = A (trans 'N', A stored n x k)
+ *                                                or A^T (trans 'T', A stored k x n).
+ *
+ * uplo 'L' ('l'): the lower triangle (i >= j) is read and written; 'U': the upper (i <= j). The
+ * other triangle is neither read nor written. One launch of the GEMM's ring kernels over the
+ * tiles that meet the triangle, the epilogue masked to it. Checks: 1 uplo, 2 trans, 3 n < 0,
+ * 4 k < 0, 6 A == NULL where read, 7 lda < max(1, rows of stored A), 9 C == NULL where touched,
+ * 10 ldc < max(1, n). alpha == 0 or k == 0: A is not read and the triangle becomes beta*C
+ * (beta == 0 writes zeros without reading C); n == 0, or that case with beta == 1: nothing is
+ * enqueued. MDG_ERR_SIZE as for mdg_dgemm.
+ */
+int mdg_dsyrk(char uplo, char trans, int64_t n, int64_t k, double alpha, const double *A,
+              int64_t lda, double beta, double *C, int64_t ldc, void *stream);
+
+/*
+ * The same with an explicit ring configuration, named by its GEMM variant id (or
+ * MDG_VARIANT_AUTO). Ids that cannot run the given triangle return MDG_ERR_VARIANT. Integer-valued
+ * data give bitwise-identical results in every accepted variant.
+ */
+int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, double alpha,
+                 const double *A, int64_t lda, double beta, double *C, int64_t ldc, void *stream);
+
+/* The GEMM variant id mdg_dsyrk would use for a product of this shape (host only), or
+ * MDG_ERR_VARIANT for invalid flags or sizes. */
+int mdg_dsyrk_select_variant(char uplo, char trans, int64_t n, int64_t k);
+
+/*
+ * Triangular matrix-matrix multiply, in place on the m x n B:
+ *
+ *     B := alpha * op(A) * B   (side 'L', A of order m)   or   B := alpha * B * op(A)   (side 'R',
+ *     A of order n),
+ *
+ * A triangular: uplo 'L' or 'U' names the stored triangle that is read (the other is not), diag
+ * 'U' takes the diagonal as ones without reading it ('N': read). transa 'N' or 'T'/'C'.
+ * Computed by recursive halving of op(A): the off-diagonal blocks by mdg_dgemm, each diagonal
+ * block of order <= 64 by one small kernel per block, all in order on `stream` (about 2m/64 or
+ * 2n/64 launches). Checks: 1 side, 2 uplo, 3 transa, 4 diag, 5 m < 0, 6 n < 0, 8 A == NULL where
+ * read, 9 lda < max(1, order of A), 10 B == NULL (m, n > 0), 11 ldb < max(1, m). Every GEMM of
+ * the recursion is checked before the first launch (MDG_ERR_SIZE if one would be refused), so a
+ * failed check enqueues nothing; an MDG_ERR_HIP from a later launch leaves B partly updated.
+ * alpha == 0: B := 0 without reading A or B. m == 0 or n == 0: nothing is enqueued. A and B must
+ * not overlap.
+ */
+int mdg_dtrmm(char side, char uplo, char transa, char diag, int64_t m, int64_t n, double alpha,
+              const double *A, int64_t lda, double *B, int64_t ldb, void *stream);
+
+/*
+ * Triangular solve with many right-hand sides, X overwriting the m x n B:
+ *
+ *     op(A) * X = alpha * B   (side 'L')   or   X * op(A) = alpha * B   (side 'R'),
+ *
+ * with A, uplo, transa, diag, the checks, the launches and the error behaviour as for
+ * mdg_dtrmm. The diagonal blocks are solved by substitution; there is no test for singularity (a
+ * zero on a non-unit diagonal divides by zero, as in the reference BLAS).
+ */
+int mdg_dtrsm(char side, char uplo, char transa, char diag, int64_t m, int64_t n, double alpha,
+              const double *A, int64_t lda, double *B, int64_t ldb, void *stream);
+
 /*
  * The raw hipError_t of the last HIP call that failed inside this library on the
  * calling thread (0 if none): the detail behind an MDG_ERR_HIP return.

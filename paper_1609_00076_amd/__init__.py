@@ -1,12 +1,14 @@
 """MI355X-native double-precision GEMM (dgemm) with hand-written gfx950 HIP kernels.
 
 C := alpha*op(A)*op(B) + beta*C on column-major operands with leading
-dimensions, exported by libmdg.so through the C ABI in include/mdg.h. This
+dimensions, and the level-3 operations built on it (dsyrk, dtrmm, dtrsm),
+exported by libmdg.so through the C ABI in include/mdg.h. This
 package is the thin Python binding (ctypes); torch supplies device memory and
 streams only.
 """
 from .binding import (MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, load, mdg_dgemm,
-                      mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_split,
+                      mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_split, mdg_dsyrk,
+                      mdg_dsyrk_ex, mdg_dsyrk_select_variant, mdg_dtrmm, mdg_dtrsm,
                       mdg_dgemm_split_workspace_size, mdg_gemm_desc, mdg_grouped_plan,
                       mdg_grouped_plan_bytes, mdg_grouped_tile_classes, mdg_last_hip_error,
                       mdg_num_variants, mdg_select_variant, mdg_split_max_slices,
@@ -15,6 +17,7 @@ from .binding import (MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, l
 
 __all__ = ["MDG_SCHEDULE_LPT", "MDG_SCHEDULE_NATURAL", "MdgError", "dgemm", "load", "mdg_dgemm",
            "mdg_dgemm_ex", "mdg_dgemm_grouped", "mdg_dgemm_split", "mdg_dgemm_split_workspace_size",
+           "mdg_dsyrk", "mdg_dsyrk_ex", "mdg_dsyrk_select_variant", "mdg_dtrmm", "mdg_dtrsm",
            "mdg_gemm_desc", "mdg_grouped_plan", "mdg_grouped_plan_bytes",
            "mdg_grouped_tile_classes", "mdg_last_hip_error", "mdg_num_variants",
            "mdg_select_variant", "mdg_split_max_slices", "mdg_split_slices", "mdg_status_string",

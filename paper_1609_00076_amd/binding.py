@@ -105,6 +105,17 @@ def load():
     lib.mdg_grouped_plan.restype = ci
     lib.mdg_dgemm_grouped.argtypes = [vp, i64, ci, vp]
     lib.mdg_dgemm_grouped.restype = ci
+    syrk_args = [ch, ch, i64, i64, dbl, vp, i64, dbl, vp, i64, vp]
+    lib.mdg_dsyrk.argtypes = syrk_args
+    lib.mdg_dsyrk.restype = ci
+    lib.mdg_dsyrk_ex.argtypes = [ci] + syrk_args
+    lib.mdg_dsyrk_ex.restype = ci
+    lib.mdg_dsyrk_select_variant.argtypes = [ch, ch, i64, i64]
+    lib.mdg_dsyrk_select_variant.restype = ci
+    for name in ("mdg_dtrmm", "mdg_dtrsm"):
+        f = getattr(lib, name)
+        f.argtypes = [ch, ch, ch, ch, i64, i64, dbl, vp, i64, vp, i64, vp]
+        f.restype = ci
     _lib = lib
     return lib
 
@@ -183,6 +194,53 @@ def mdg_dgemm_ex(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, 
     """mdg_dgemm with an explicit kernel variant (or -1 for automatic choice)."""
     return load().mdg_dgemm_ex(int(variant), *_marshal(transa, transb, m, n, k, alpha, A, lda, B,
                                                        ldb, beta, C, ldc, stream))
+
+
+def _marshal_syrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream):
+    reads_a = n > 0 and alpha != 0.0 and k > 0
+    touches_c = n > 0 and not ((alpha == 0.0 or k <= 0) and beta == 1.0)
+    ra, ca = (k, n) if _is_trans(trans) else (n, k)
+    need_a = _extent(ra, ca, lda) if reads_a and lda >= max(1, ra) else 0
+    need_c = _extent(n, n, ldc) if touches_c and ldc >= max(1, n) else 0
+    return (_ch(uplo), _ch(trans), int(n), int(k), float(alpha), _ptr(A, need_a, "A"), int(lda),
+            float(beta), _ptr(C, need_c, "C"), int(ldc), _stream(stream) if touches_c else None)
+
+
+def mdg_dsyrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None) -> int:
+    """C := alpha*op(A)*op(A)^T + beta*C on the `uplo` triangle of C."""
+    return load().mdg_dsyrk(*_marshal_syrk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream))
+
+
+def mdg_dsyrk_ex(variant, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream=None) -> int:
+    """mdg_dsyrk with the ring configuration of an explicit GEMM variant id (or -1)."""
+    return load().mdg_dsyrk_ex(int(variant), *_marshal_syrk(uplo, trans, n, k, alpha, A, lda, beta,
+                                                            C, ldc, stream))
+
+
+def mdg_dsyrk_select_variant(uplo, trans, n, k) -> int:
+    return load().mdg_dsyrk_select_variant(_ch(uplo), _ch(trans), int(n), int(k))
+
+
+def _marshal_tri(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream):
+    empty = m <= 0 or n <= 0
+    na = m if _ch(side) in (b"L", b"l") else n
+    need_a = _extent(na, na, lda) if not empty and alpha != 0.0 and lda >= max(1, na) else 0
+    need_b = _extent(m, n, ldb) if not empty and ldb >= max(1, m) else 0
+    return (_ch(side), _ch(uplo), _ch(transa), _ch(diag), int(m), int(n), float(alpha),
+            _ptr(A, need_a, "A"), int(lda), _ptr(B, need_b, "B"), int(ldb),
+            None if empty else _stream(stream))
+
+
+def mdg_dtrmm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream=None) -> int:
+    """B := alpha*op(A)*B (side L) or alpha*B*op(A) (side R), A triangular."""
+    return load().mdg_dtrmm(*_marshal_tri(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb,
+                                          stream))
+
+
+def mdg_dtrsm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream=None) -> int:
+    """Solve op(A)*X = alpha*B (side L) or X*op(A) = alpha*B (side R); X overwrites B."""
+    return load().mdg_dtrsm(*_marshal_tri(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb,
+                                          stream))
 
 
 def mdg_select_variant(transa, transb, m, n, k, alpha, beta) -> int:

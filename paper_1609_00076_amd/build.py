@@ -7,7 +7,8 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB_PATH = os.path.join(PKG, "libmdg.so")
-SOURCES = [os.path.join(PKG, "csrc", "mdg_dgemm.hip"), os.path.join(PKG, "csrc", "mdg_split.hip")]
+SOURCES = [os.path.join(PKG, "csrc", "mdg_dgemm.hip"), os.path.join(PKG, "csrc", "mdg_split.hip"),
+           os.path.join(PKG, "csrc", "mdg_blas3.hip")]
 INCLUDE = os.path.join(ROOT, "include")
 
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

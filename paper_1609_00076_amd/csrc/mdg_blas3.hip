@@ -1,0 +1,380 @@
+// mdg_blas3.hip -- triangular multiply (dtrmm) and triangular solve (dtrsm) built on the GEMM.
+//
+// The paper's Step 2 ("Poorman's BLAS") observes that once GEMM on submatrices is fast, the rest
+// of the level-3 BLAS can be cast in terms of it (Kagstrom, Ling and Van Loan). Both operations
+// here split the triangle recursively into halves,
+//
+//     op(A) = [T11  0 ]   or   [T11 T12]
+//             [T21 T22]        [ 0  T22],
+//
+// so that all but the diagonal blocks' work is GEMM on submatrices, run by mdg_dgemm on the
+// caller's stream. Each diagonal block of order <= kLeaf is finished by one small kernel that
+// keeps the block in LDS and holds one right-hand side (a column of B for side 'L', a row for
+// side 'R') per lane.
+//
+// Multiply, side 'L', lower op(A):  B2 := alpha T22 B2;  B2 += alpha T21 B1;  B1 := alpha T11 B1.
+// Solve,    side 'L', lower op(A):  X1 from T11 X1 = alpha B1;  B2 := alpha B2 - T21 X1;
+//                                    X2 from T22 X2 = B2.
+// The other cases mirror these (upper op(A) reverses the order; side 'R' works on column blocks
+// of B with the operands of the GEMM swapped). Every step updates B in place, and the order
+// makes every GEMM read only blocks that are final or not yet touched, as the step needs them.
+//
+// Before any launch the whole sequence of steps is planned on the host and every GEMM in it is
+// checked as mdg_dgemm would check it, so a call that fails its checks enqueues nothing.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "mdg.h"
+#include "mdg_internal.h"
+
+namespace mdg_blas3 {
+
+constexpr int kLeaf = 64;  // order of the diagonal blocks the leaf kernel finishes
+
+// One diagonal block: for each of `nvec` vectors y of length nb <= kLeaf,
+//   multiply: y := alpha * M * y        solve: y := M^{-1} (alpha * y),
+// with M the nb x nb block seen as lower (or upper) triangular, element (i, p) at
+// Ablk[p * lda + i] (mt == 0) or Ablk[i * lda + p] (mt == 1), and diagonal 1 when `unit` (then
+// the stored diagonal is not read). Element i of vector v is Y[v * vs + i * es].
+struct LeafArgs {
+  const double* A;
+  int64_t lda;
+  double* Y;
+  int64_t es, vs, nvec;
+  double alpha;
+  int nb, mt, unit;
+};
+
+// Workgroup of 64 lanes; lane w owns vector 64 * blockIdx.x + w. The block of M (the identity
+// outside the nb x nb corner and zero outside the triangle, so the other triangle is never read)
+// and the 64 vectors are staged in LDS with loads along whichever index is contiguous in memory.
+template <bool SOLVE, bool LOWER>
+__device__ __forceinline__ void leaf_body(const LeafArgs& a) {
+  __shared__ double Ms[kLeaf][kLeaf + 1];
+  __shared__ double Ys[kLeaf][kLeaf + 1];
+  const int lane = threadIdx.x;
+  const int64_t v0 = (int64_t)blockIdx.x * kLeaf;
+
+  // M: lanes run along the stored index that is contiguous (rows of the stored block).
+  for (int outer = 0; outer < kLeaf; ++outer) {
+    const int i = a.mt ? outer : lane;  // M row
+    const int p = a.mt ? lane : outer;  // M column
+    const bool in_tri = LOWER ? p <= i : p >= i;
+    double x = (i == p) ? 1.0 : 0.0;
+    if (i < a.nb && p < a.nb && in_tri && !(i == p && a.unit))
+      x = a.mt ? a.A[(int64_t)i * a.lda + p] : a.A[(int64_t)p * a.lda + i];
+    Ms[i][p] = x;
+  }
+  // The vectors, zero beyond nb elements or beyond the last vector.
+  const bool elem_contig = a.es == 1;
+  for (int outer = 0; outer < kLeaf; ++outer) {
+    const int w = elem_contig ? outer : lane;
+    const int i = elem_contig ? lane : outer;
+    const int64_t v = v0 + w;
+    Ys[w][i] = (v < a.nvec && i < a.nb) ? a.Y[v * a.vs + (int64_t)i * a.es] : 0.0;
+  }
+  __syncthreads();
+
+  double y[kLeaf];
+#pragma unroll
+  for (int i = 0; i < kLeaf; ++i) y[i] = Ys[lane][i];
+  const double alpha = a.alpha;
+
+  if (SOLVE) {
+    // Substitution in the order the triangle allows: y_i depends on y_p for p before i.
+#pragma unroll
+    for (int t = 0; t < kLeaf; ++t) {
+      const int i = LOWER ? t : kLeaf - 1 - t;
+      double s = 0.0;
+#pragma unroll
+      for (int p = LOWER ? 0 : i + 1; p < (LOWER ? i : kLeaf); ++p) s += Ms[i][p] * y[p];
+      const double r = alpha * y[i] - s;
+      y[i] = a.unit ? r : r / Ms[i][i];
+    }
+  } else {
+    // In place: row i reads y_p on its own side of the diagonal only, so the rows are done in
+    // the order that leaves those entries unchanged until read.
+#pragma unroll
+    for (int t = 0; t < kLeaf; ++t) {
+      const int i = LOWER ? kLeaf - 1 - t : t;
+      double s = 0.0;
+#pragma unroll
+      for (int p = LOWER ? 0 : i; p <= (LOWER ? i : kLeaf - 1); ++p) s += Ms[i][p] * y[p];
+      y[i] = alpha * s;
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < kLeaf; ++i) Ys[lane][i] = y[i];
+  __syncthreads();
+  for (int outer = 0; outer < kLeaf; ++outer) {
+    const int w = elem_contig ? outer : lane;
+    const int i = elem_contig ? lane : outer;
+    const int64_t v = v0 + w;
+    if (v < a.nvec && i < a.nb) a.Y[v * a.vs + (int64_t)i * a.es] = Ys[w][i];
+  }
+}
+
+__global__ void __launch_bounds__(64) leaf_mul_lower(LeafArgs a) { leaf_body<false, true>(a); }
+__global__ void __launch_bounds__(64) leaf_mul_upper(LeafArgs a) { leaf_body<false, false>(a); }
+__global__ void __launch_bounds__(64) leaf_solve_lower(LeafArgs a) { leaf_body<true, true>(a); }
+__global__ void __launch_bounds__(64) leaf_solve_upper(LeafArgs a) { leaf_body<true, false>(a); }
+
+// B := 0 over the logical m x n matrix (the alpha == 0 case; A and B are not read).
+__global__ void __launch_bounds__(256) zero_kernel(int64_t m, int64_t n, double* B, int64_t ldb) {
+  const int64_t total = m * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / m, i = e - j * m;
+    B[j * ldb + i] = 0.0;
+  }
+}
+
+// ---- host side ---------------------------------------------------------------------------------
+
+bool is_notrans(char t) { return t == 'N' || t == 'n'; }
+bool is_trans(char t) { return t == 'T' || t == 't' || t == 'C' || t == 'c'; }
+bool is_lower(char u) { return u == 'L' || u == 'l'; }
+bool is_upper(char u) { return u == 'U' || u == 'u'; }
+bool is_left(char s) { return s == 'L' || s == 'l'; }
+bool is_right(char s) { return s == 'R' || s == 'r'; }
+bool is_unit(char d) { return d == 'U' || d == 'u'; }
+bool is_nonunit(char d) { return d == 'N' || d == 'n'; }
+int64_t max1(int64_t x) { return x > 1 ? x : 1; }
+
+struct GemmStep {
+  char ta, tb;
+  int64_t m, n, k;
+  double alpha;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double beta;
+  double* C;
+  int64_t ldc;
+};
+
+struct Step {
+  bool is_gemm;
+  GemmStep g;   // when is_gemm
+  LeafArgs leaf;  // otherwise
+};
+
+struct Problem {
+  bool left, op_lower, ta, unit, solve;
+  const double* A;
+  int64_t lda;
+  double* B;
+  int64_t ldb, m, n;
+  std::vector<Step> steps;
+
+  // op(A)(r.., c..) as a GEMM operand: the pointer and transpose flag of the stored block.
+  const double* opa(int64_t r, int64_t c, char* t) const {
+    *t = ta ? 'T' : 'N';
+    return ta ? A + r * lda + c : A + c * lda + r;
+  }
+  // Leading block of B for the diagonal range starting at `off`: rows (side L) or columns (R).
+  double* bblk(int64_t off) const { return left ? B + off : B + off * ldb; }
+
+  void leaf(int64_t off, int64_t nb, double alpha) {
+    Step s{};
+    s.is_gemm = false;
+    LeafArgs& a = s.leaf;
+    a.A = A + off * lda + off;
+    a.lda = lda;
+    a.Y = bblk(off);
+    a.es = left ? 1 : ldb;   // side L: columns of B; side R: rows of B
+    a.vs = left ? ldb : 1;
+    a.nvec = left ? n : m;
+    a.alpha = alpha;
+    a.nb = (int)nb;
+    a.mt = left ? (ta ? 1 : 0) : (ta ? 0 : 1);  // side R works with the block's transpose
+    a.unit = unit ? 1 : 0;
+    steps.push_back(s);
+  }
+
+  // C_blk := ga * X * Y + gb * C_blk with the blocks of the recursion; X, Y are given by
+  // (pointer, transpose, leading dimension).
+  void gemm(int64_t m_, int64_t n_, int64_t k_, double ga, const double* X, char tx, int64_t ldx,
+            const double* Y, char ty, int64_t ldy, double gb, double* C, int64_t ldc) {
+    Step s{};
+    s.is_gemm = true;
+    s.g = GemmStep{tx, ty, m_, n_, k_, ga, X, ldx, Y, ldy, gb, C, ldc};
+    steps.push_back(s);
+  }
+
+  // The diagonal range [off, off + na) of op(A) and the matching part of B, scaled by alpha.
+  void rec(int64_t off, int64_t na, double alpha) {
+    if (na <= kLeaf) {
+      leaf(off, na, alpha);
+      return;
+    }
+    const int64_t leaves = (na + kLeaf - 1) / kLeaf;
+    const int64_t h = (leaves + 1) / 2 * kLeaf;  // first half: whole leaves
+    const int64_t o1 = off, o2 = off + h, n1 = h, n2 = na - h;
+    char t;
+    // Off-diagonal block of op(A): T21 = op(A)(o2.., o1..) when lower, T12 = op(A)(o1.., o2..).
+    const double* T = op_lower ? opa(o2, o1, &t) : opa(o1, o2, &t);
+    double* B1 = bblk(o1);
+    double* B2 = bblk(o2);
+    if (!solve) {
+      if (left) {
+        // Lower: B2 := a T22 B2 + a T21 B1 then B1 := a T11 B1. Upper: B1 first, using B2.
+        if (op_lower) {
+          rec(o2, n2, alpha);
+          gemm(n2, n, n1, alpha, T, t, lda, B1, 'N', ldb, 1.0, B2, ldb);
+          rec(o1, n1, alpha);
+        } else {
+          rec(o1, n1, alpha);
+          gemm(n1, n, n2, alpha, T, t, lda, B2, 'N', ldb, 1.0, B1, ldb);
+          rec(o2, n2, alpha);
+        }
+      } else {
+        // B op(A), B = [B1 B2] by columns. Lower: B1 := a B1 T11 + a B2 T21, B2 := a B2 T22.
+        // Upper: B2 := a B1 T12 + a B2 T22, B1 := a B1 T11.
+        if (op_lower) {
+          rec(o1, n1, alpha);
+          gemm(m, n1, n2, alpha, B2, 'N', ldb, T, t, lda, 1.0, B1, ldb);
+          rec(o2, n2, alpha);
+        } else {
+          rec(o2, n2, alpha);
+          gemm(m, n2, n1, alpha, B1, 'N', ldb, T, t, lda, 1.0, B2, ldb);
+          rec(o1, n1, alpha);
+        }
+      }
+    } else {
+      if (left) {
+        // Lower: X1 from T11; B2 := a B2 - T21 X1; X2 from T22. Upper: the reverse.
+        if (op_lower) {
+          rec(o1, n1, alpha);
+          gemm(n2, n, n1, -1.0, T, t, lda, B1, 'N', ldb, alpha, B2, ldb);
+          rec(o2, n2, 1.0);
+        } else {
+          rec(o2, n2, alpha);
+          gemm(n1, n, n2, -1.0, T, t, lda, B2, 'N', ldb, alpha, B1, ldb);
+          rec(o1, n1, 1.0);
+        }
+      } else {
+        // X op(A) = a B. Lower: X2 from T22; B1 := a B1 - X2 T21; X1 from T11.
+        // Upper: X1 from T11; B2 := a B2 - X1 T12; X2 from T22.
+        if (op_lower) {
+          rec(o2, n2, alpha);
+          gemm(m, n1, n2, -1.0, B2, 'N', ldb, T, t, lda, alpha, B1, ldb);
+          rec(o1, n1, 1.0);
+        } else {
+          rec(o1, n1, alpha);
+          gemm(m, n2, n1, -1.0, B1, 'N', ldb, T, t, lda, alpha, B2, ldb);
+          rec(o2, n2, 1.0);
+        }
+      }
+    }
+  }
+};
+
+int launch_leaf(const Problem& p, const LeafArgs& a, hipStream_t s) {
+  const void* fn = p.solve ? (p.op_lower == p.left ? reinterpret_cast<const void*>(&leaf_solve_lower)
+                                                   : reinterpret_cast<const void*>(&leaf_solve_upper))
+                           : (p.op_lower == p.left ? reinterpret_cast<const void*>(&leaf_mul_lower)
+                                                   : reinterpret_cast<const void*>(&leaf_mul_upper));
+  LeafArgs arg = a;
+  void* argv[] = {&arg};
+  const int64_t blocks = (a.nvec + kLeaf - 1) / kLeaf;
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kLeaf), argv, 0, s);
+  if (e != hipSuccess) {
+    mdg_record_hip_error((int)e);
+    return MDG_ERR_HIP;
+  }
+  return MDG_SUCCESS;
+}
+
+// Shared by dtrmm and dtrsm: argument checks in level-3 BLAS order, then plan, check, run.
+int tri_op(bool solve, char side, char uplo, char transa, char diag, int64_t m, int64_t n,
+           double alpha, const double* A, int64_t lda, double* B, int64_t ldb, void* stream) {
+  if (!is_left(side) && !is_right(side)) return 1;
+  if (!is_lower(uplo) && !is_upper(uplo)) return 2;
+  if (!is_notrans(transa) && !is_trans(transa)) return 3;
+  if (!is_unit(diag) && !is_nonunit(diag)) return 4;
+  if (m < 0) return 5;
+  if (n < 0) return 6;
+  const bool empty = (m == 0 || n == 0);
+  const int64_t na = is_left(side) ? m : n;
+  if (!empty && alpha != 0.0 && A == nullptr) return 8;
+  if (lda < max1(na)) return 9;
+  if (!empty && B == nullptr) return 10;
+  if (ldb < max1(m)) return 11;
+  if (empty) return MDG_SUCCESS;
+  // A leaf launch has one lane per right-hand side: at most INT32_MAX of them.
+  if ((is_left(side) ? n : m) > (int64_t)INT32_MAX) return MDG_ERR_SIZE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  if (alpha == 0.0) {
+    const int dc = mdg_device_check();
+    if (dc) return dc;
+    const int64_t blocks = (m * n + 255) / 256 < 65536 ? (m * n + 255) / 256 : 65536;
+    int64_t mm = m, nn = n, ld = ldb;
+    double* b = B;
+    void* argv[] = {&mm, &nn, &b, &ld};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&zero_kernel),
+                                   dim3((unsigned)blocks), dim3(256), argv, 0, s);
+    if (e != hipSuccess) {
+      mdg_record_hip_error((int)e);
+      return MDG_ERR_HIP;
+    }
+    return MDG_SUCCESS;
+  }
+
+  Problem p;
+  p.left = is_left(side);
+  p.ta = is_trans(transa);
+  p.op_lower = is_lower(uplo) != p.ta;
+  p.unit = is_unit(diag);
+  p.solve = solve;
+  p.A = A;
+  p.lda = lda;
+  p.B = B;
+  p.ldb = ldb;
+  p.m = m;
+  p.n = n;
+  p.rec(0, na, alpha);
+
+  for (const Step& st : p.steps) {
+    if (!st.is_gemm) continue;
+    const GemmStep& g = st.g;
+    const int c = mdg_dgemm_precheck(g.ta, g.tb, g.m, g.n, g.k, g.alpha, g.A, g.lda, g.B, g.ldb,
+                                     g.beta, g.C, g.ldc);
+    if (c > 0) return MDG_ERR_SIZE;  // not reachable with valid arguments; refuse all the same
+    if (c < 0) return c;
+  }
+  const int dc = mdg_device_check();
+  if (dc) return dc;
+  for (const Step& st : p.steps) {
+    int r;
+    if (st.is_gemm) {
+      const GemmStep& g = st.g;
+      r = mdg_dgemm(g.ta, g.tb, g.m, g.n, g.k, g.alpha, g.A, g.lda, g.B, g.ldb, g.beta, g.C, g.ldc,
+                    stream);
+    } else {
+      r = launch_leaf(p, st.leaf, s);
+    }
+    if (r) return r;
+  }
+  return MDG_SUCCESS;
+}
+
+}  // namespace mdg_blas3
+
+extern "C" {
+
+int mdg_dtrmm(char side, char uplo, char transa, char diag, int64_t m, int64_t n, double alpha,
+              const double* A, int64_t lda, double* B, int64_t ldb, void* stream) {
+  return mdg_blas3::tri_op(false, side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream);
+}
+
+int mdg_dtrsm(char side, char uplo, char transa, char diag, int64_t m, int64_t n, double alpha,
+              const double* A, int64_t lda, double* B, int64_t ldb, void* stream) {
+  return mdg_blas3::tri_op(true, side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream);
+}
+}  // extern "C"

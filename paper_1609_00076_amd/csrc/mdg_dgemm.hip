@@ -518,7 +518,9 @@ __device__ __forceinline__ void ring_mask_tail(double* st, int k_left) {
 }
 
 // Tile (tm, tn) of C by one workgroup of a ring configuration; `smem` holds R::LDS_DOUBLES.
-template <class R, bool TA, bool TB>
+// TRI restricts the epilogue to one triangle of C (0: all of it; 1: i >= j; 2: i <= j): entries
+// outside it are neither read nor written.
+template <class R, bool TA, bool TB, int TRI = 0>
 __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, double* smem) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -713,7 +715,8 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
         for (int bi = 0; bi < R::BM; ++bi) {
           const int64_t i = row_of(bi);
-          cb[bi][r] = (col_ok && i < g.m) ? g.C[j * g.ldc + i] : 0.0;
+          const bool tri_ok = TRI == 0 || (TRI == 1 ? i >= j : i <= j);
+          cb[bi][r] = (col_ok && i < g.m && tri_ok) ? g.C[j * g.ldc + i] : 0.0;
         }
       }
     }
@@ -724,7 +727,8 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
       for (int bi = 0; bi < R::BM; ++bi) {
         const int64_t i = row_of(bi);
-        if (i < g.m) {
+        const bool tri_ok = TRI == 0 || (TRI == 1 ? i >= j : i <= j);
+        if (i < g.m && tri_ok) {
           const double v = alpha * acc[bi][bj2][r];
           g.C[j * g.ldc + i] = (beta != 0.0) ? v + beta * cb[bi][r] : v;
         }
@@ -740,6 +744,55 @@ dgemm_ring_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   int tm, tn;
   if (!tile_coords<R::GROUP>(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
   ring_tile<R, TA, TB>(g, tm, tn, smem);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Symmetric rank-k update C := alpha*op(A)*op(A)^T + beta*C on one triangle of C: the GEMM with
+// B = A (transb the opposite of trans) over only the tiles that meet the triangle, each computed
+// by the ring tile with its epilogue masked to the triangle.
+//
+// Those tiles are numbered t = 0, 1, ...: for the lower triangle row by row, tile row a holding
+// tile columns 0 .. q(a+1)-1 with q = MT/NT; for the upper triangle column by column, tile column
+// a holding tile rows 0 .. q(a+1)-1 with q = NT/MT (q is 1 or 2). Before line a come
+// P(a) = q a (a+1) / 2 tiles. Only the last line can be cut short by the edge of C, so the count
+// is exact for every earlier line.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void tri_decode(int t, int q, int& a, int& b) {
+  int x = (int)((sqrt(1.0 + 8.0 * (double)t / q) - 1.0) * 0.5);
+  while ((int64_t)q * (x + 1) * (x + 2) / 2 <= t) ++x;  // correct a rounding of the root
+  while (x > 0 && (int64_t)q * x * (x + 1) / 2 > t) --x;
+  a = x;
+  b = t - q * x * (x + 1) / 2;
+}
+
+template <class R, bool TA, bool TB, int TRI>
+__global__ void __launch_bounds__(R::THREADS) __attribute__((amdgpu_waves_per_eu(R::MIN_WAVES_PER_EU)))
+dsyrk_ring_kernel(GemmArgs g, int tiles) {
+  static_assert(TRI == 1 || TRI == 2, "one triangle");
+  constexpr int q = TRI == 1 ? R::MT / R::NT : R::NT / R::MT;
+  static_assert(q >= 1 && (TRI == 1 ? R::MT == q * R::NT : R::NT == q * R::MT),
+                "tile aspect ratio 1 or 2 along the enumerated lines");
+  __shared__ __attribute__((aligned(16))) double smem[R::LDS_DOUBLES];
+  // Contiguous ranges of t per XCD, as in tile_coords (the grid is a multiple of kXcds).
+  const int t = (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+  if (t >= tiles) return;
+  int a, b;
+  tri_decode(t, q, a, b);
+  ring_tile<R, TA, TB, TRI>(g, TRI == 1 ? a : b, TRI == 1 ? b : a, smem);
+}
+
+// C := beta*C on one triangle of the n x n C (lower: i >= j, else i <= j); beta == 0 writes zeros
+// without reading C. The whole update when alpha == 0 or k == 0.
+__global__ void __launch_bounds__(256) scale_tri_kernel(int64_t n, int lower, double beta,
+                                                        double* C, int64_t ldc) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / n, i = e - j * n;
+    if (lower ? i < j : i > j) continue;
+    double* c = C + j * ldc + i;
+    *c = (beta == 0.0) ? 0.0 : beta * *c;
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -861,6 +914,34 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// Ring configurations that run the symmetric rank-k update, per triangle. Each is named by the
+// GEMM variant with the same configuration, whose tile shape, residency and measured
+// efficiencies the choice uses.
+typedef void (*SyrkFn)(GemmArgs, int);
+
+struct SyrkVariant {
+  const char* name;  // the variant of kVariants with this ring configuration
+  int tri;           // 1: lower triangle, 2: upper
+  SyrkFn fn[2];      // [trans]: 'N' runs the GEMM case NT, 'T' the case TN
+};
+
+template <class R, int TRI>
+constexpr SyrkVariant make_syrk_variant(const char* name) {
+  return SyrkVariant{name, TRI,
+                     {dsyrk_ring_kernel<R, false, true, TRI>, dsyrk_ring_kernel<R, true, false, TRI>}};
+}
+
+const SyrkVariant kSyrkVariants[] = {
+    make_syrk_variant<Ring256x128t, 1>("ring_f64_256x128x16_w128x32_s3_il"),
+    make_syrk_variant<Ring128x64, 1>("ring_f64_128x64x16_w32x32_s3_il"),
+    make_syrk_variant<Ring128x4i, 1>("ring_f64_128x128x16_w32x32_s4_il"),
+    make_syrk_variant<Ring64s3, 1>("ring_f64_64x64x16_w32x32_s3_il"),
+    make_syrk_variant<Ring128x256wi, 2>("ring_f64_128x256x16_w64x64_s3_il"),
+    make_syrk_variant<Ring128x4i, 2>("ring_f64_128x128x16_w32x32_s4_il"),
+    make_syrk_variant<Ring64s3, 2>("ring_f64_64x64x16_w32x32_s3_il"),
+};
+constexpr int kNumSyrkVariants = sizeof(kSyrkVariants) / sizeof(kSyrkVariants[0]);
 
 // ------------------------------------------------------------------------------------------------
 // Grouped launch: many independent GEMMs in one persistent kernel.
@@ -1064,6 +1145,59 @@ int launch(const void* fn, dim3 grid, dim3 block, hipStream_t s, Args... args) {
   return e == hipSuccess ? MDG_SUCCESS : hip_fail(e);
 }
 
+// ---- symmetric rank-k update: host side ----------------------------------------------------------
+
+bool is_lower(char u) { return u == 'L' || u == 'l'; }
+bool is_upper(char u) { return u == 'U' || u == 'u'; }
+
+int variant_by_name(const char* name) {
+  for (int v = 0; v < kNumVariants; ++v)
+    if (std::strcmp(kVariants[v].name, name) == 0) return v;
+  return -1;
+}
+
+// Tiles of one triangle (1 lower, 2 upper) of an n x n C with mt x nt tiles, counted as the
+// kernel numbers them: q a (a+1) / 2 before the last line a, and that line cut at the edge.
+int64_t syrk_tiles(int tri, int64_t n, int mt, int nt) {
+  const int64_t tiles_m = ceil_div(n, mt), tiles_n = ceil_div(n, nt);
+  const int64_t lines = tri == 1 ? tiles_m : tiles_n, across = tri == 1 ? tiles_n : tiles_m;
+  const int64_t q = tri == 1 ? mt / nt : nt / mt;
+  const int64_t a = lines - 1;
+  const int64_t last = q * (a + 1) < across ? q * (a + 1) : across;
+  return q * a * (a + 1) / 2 + last;
+}
+
+// The entry of kSyrkVariants for triangle `tri` with the smallest estimated time under the GEMM
+// cost model (pick_variant), over the triangle's tiles; `only` >= 0 restricts the choice to the
+// entry named like kVariants[only]. Returns -1 if none qualifies.
+int pick_syrk(int tri, bool ta, int64_t n, int64_t k, int only) {
+  int best = -1;
+  double best_cost = 0.0;
+  const bool short_k = k <= kShortK;
+  for (int s = 0; s < kNumSyrkVariants; ++s) {
+    const SyrkVariant& sv = kSyrkVariants[s];
+    if (sv.tri != tri) continue;
+    const int vid = variant_by_name(sv.name);
+    if (vid < 0 || (only >= 0 && vid != only)) continue;
+    const Variant& var = kVariants[vid];
+    int eff = short_k ? var.short_k_permil : var.eff_permil[ta][!ta];
+    if (eff <= 0 && only >= 0) eff = 1;  // an explicit choice runs even if never automatic
+    if (eff <= 0) continue;
+    const int64_t tiles = syrk_tiles(tri, n, var.mt, var.nt);
+    const int64_t per_cu = ceil_div(tiles, kCUs);
+    const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
+    const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
+    const double overhead = short_k ? 0.0 : kTileOverheadK / resident;
+    const double cost = (double)per_cu * var.mt * var.nt * ((double)k + overhead) /
+                        (eff * 1e-3 * occupancy);
+    if (best < 0 || cost < best_cost) {
+      best = s;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 }  // namespace mdg_impl
 
 using namespace mdg_impl;
@@ -1121,9 +1255,17 @@ int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k
   return pick_variant(is_trans(transa), is_trans(transb), m, n, k);
 }
 
-int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
-                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                 double beta, double* C, int64_t ldc, void* stream) {
+}  // extern "C"
+
+namespace mdg_impl {
+
+// Every check mdg_dgemm_ex makes before its first HIP call. Returns the status it would return
+// there (nonzero), or 0 with *vid the variant to launch (-1: the alpha == 0 / k == 0 scaling,
+// -2: nothing to enqueue).
+int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double beta, const double* C, int64_t ldc, int* vid) {
+  *vid = -2;
   const int info = check_args(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   if (info) return info;
   if (variant != MDG_VARIANT_AUTO && (variant < 0 || variant >= kNumVariants))
@@ -1131,19 +1273,44 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
   if (m == 0 || n == 0) return MDG_SUCCESS;
   const bool no_product = (alpha == 0.0 || k == 0);
   if (no_product && beta == 1.0) return MDG_SUCCESS;
-
-  int vid = -1;
-  if (!no_product) {  // host-side checks of the launch shape, before any HIP call
-    vid = (variant == MDG_VARIANT_AUTO)
-              ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
-              : variant;
-    const Variant& v = kVariants[vid];
-    if (ceil_div(m, v.mt) * ceil_div(n, v.nt) > (int64_t)INT32_MAX / 1024)
-      return MDG_ERR_SIZE;  // beyond one launch's grid
-    if (!panel_offsets_fit(is_trans(transa), is_trans(transb), v.mt, v.nt, v.kt, m, n, k, lda,
-                           ldb))
-      return MDG_ERR_SIZE;
+  if (no_product) {
+    *vid = -1;
+    return MDG_SUCCESS;
   }
+  const int v_id = (variant == MDG_VARIANT_AUTO)
+                       ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
+                       : variant;
+  const Variant& v = kVariants[v_id];
+  if (ceil_div(m, v.mt) * ceil_div(n, v.nt) > (int64_t)INT32_MAX / 1024)
+    return MDG_ERR_SIZE;  // beyond one launch's grid
+  if (!panel_offsets_fit(is_trans(transa), is_trans(transb), v.mt, v.nt, v.kt, m, n, k, lda, ldb))
+    return MDG_ERR_SIZE;
+  *vid = v_id;
+  return MDG_SUCCESS;
+}
+
+}  // namespace mdg_impl
+
+int mdg_dgemm_precheck(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                       const double* C, int64_t ldc) {
+  int vid;
+  return dgemm_prepare(MDG_VARIANT_AUTO, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                       ldc, &vid);
+}
+
+int mdg_device_check(void) { return device_check(); }
+
+extern "C" {
+
+int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
+                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double beta, double* C, int64_t ldc, void* stream) {
+  int vid;
+  const int st = dgemm_prepare(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                               ldc, &vid);
+  if (st || vid == -2) return st;
+  const bool no_product = vid == -1;
   const int dc = device_check();
   if (dc) return dc;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1173,6 +1340,69 @@ int mdg_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double 
               int64_t ldc, void* stream) {
   return mdg_dgemm_ex(MDG_VARIANT_AUTO, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
                       ldc, stream);
+}
+
+int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, double alpha,
+                 const double* A, int64_t lda, double beta, double* C, int64_t ldc,
+                 void* stream) {
+  if (!is_lower(uplo) && !is_upper(uplo)) return 1;
+  if (!is_notrans(trans) && !is_trans(trans)) return 2;
+  if (n < 0) return 3;
+  if (k < 0) return 4;
+  const bool ta = is_trans(trans);
+  const bool no_product = (alpha == 0.0 || k == 0);
+  if (n > 0 && !no_product && A == nullptr) return 6;
+  if (lda < max1(ta ? k : n)) return 7;
+  const bool touches_c = n > 0 && !(no_product && beta == 1.0);
+  if (touches_c && C == nullptr) return 9;
+  if (ldc < max1(n)) return 10;
+  if (variant != MDG_VARIANT_AUTO && (variant < 0 || variant >= kNumVariants))
+    return MDG_ERR_VARIANT;
+  if (!touches_c) return MDG_SUCCESS;
+  const int tri = is_lower(uplo) ? 1 : 2;
+
+  int s_idx = -1;
+  int64_t tiles = 0;
+  if (!no_product) {
+    s_idx = pick_syrk(tri, ta, n, k, variant);
+    if (s_idx < 0) return MDG_ERR_VARIANT;
+    const Variant& v = kVariants[variant_by_name(kSyrkVariants[s_idx].name)];
+    tiles = syrk_tiles(tri, n, v.mt, v.nt);
+    if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;
+    if (!panel_offsets_fit(ta, !ta, v.mt, v.nt, v.kt, n, n, k, lda, lda)) return MDG_ERR_SIZE;
+  } else if (variant != MDG_VARIANT_AUTO && pick_syrk(tri, ta, n, 1024, variant) < 0) {
+    return MDG_ERR_VARIANT;
+  }
+  const int dc = device_check();
+  if (dc) return dc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  if (no_product) {
+    const int64_t blocks = ceil_div(n * n, 256) < 65536 ? ceil_div(n * n, 256) : 65536;
+    return launch(reinterpret_cast<const void*>(&scale_tri_kernel), dim3((unsigned)blocks),
+                  dim3(256), s, n, tri == 1 ? 1 : 0, beta, C, ldc);
+  }
+  const SyrkVariant& sv = kSyrkVariants[s_idx];
+  const Variant& v = kVariants[variant_by_name(sv.name)];
+  const int64_t rows_a = ta ? k : n, cols_a = ta ? n : k;
+  const int64_t ext = (cols_a - 1) * lda + rows_a;
+  GemmArgs g{n, n, k, lda, lda, ldc, alpha, beta, A, A, C, ext, ext};
+  const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;
+  return launch(reinterpret_cast<const void*>(sv.fn[ta ? 1 : 0]), dim3((unsigned)grid),
+                dim3(v.threads), s, g, (int)tiles);
+}
+
+int mdg_dsyrk(char uplo, char trans, int64_t n, int64_t k, double alpha, const double* A,
+              int64_t lda, double beta, double* C, int64_t ldc, void* stream) {
+  return mdg_dsyrk_ex(MDG_VARIANT_AUTO, uplo, trans, n, k, alpha, A, lda, beta, C, ldc, stream);
+}
+
+int mdg_dsyrk_select_variant(char uplo, char trans, int64_t n, int64_t k) {
+  if ((!is_lower(uplo) && !is_upper(uplo)) || (!is_notrans(trans) && !is_trans(trans)) ||
+      n < 0 || k < 0)
+    return MDG_ERR_VARIANT;
+  const int s_idx = pick_syrk(is_lower(uplo) ? 1 : 2, is_trans(trans), n, k, -1);
+  return s_idx < 0 ? MDG_ERR_VARIANT : variant_by_name(kSyrkVariants[s_idx].name);
 }
 
 

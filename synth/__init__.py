@@ -125,3 +125,35 @@ def log_uniform_int(gen: np.random.Generator, lo: int, hi: int, size) -> np.ndar
     """floor(exp(U[ln lo, ln(hi+1)))) clipped to [lo, hi]."""
     x = np.floor(np.exp(gen.uniform(math.log(lo), math.log(hi + 1), size))).astype(np.int64)
     return np.clip(x, lo, hi)
+
+
+def triangular(seed: int, order: int, ld: int, uplo: str, dist: str = "uniform",
+               unit: bool = False) -> np.ndarray:
+    """Flat storage of a seeded order x order triangular matrix for dtrmm / dtrsm.
+
+    The triangle named by `uplo` holds the values; every entry of the other triangle and of the
+    padding rows is a quiet NaN, and with `unit` so is the diagonal (none of them may be read).
+    uniform: off-diagonal Uniform[-1, 1) / order, diagonal of magnitude Uniform[1, 2) with a
+             random sign (a well-conditioned triangle)
+    int:     off-diagonal integers in {-4, ..., 4}, diagonal in {-4, -2, -1, 1, 2, 4} (so that a
+             solve with integer right-hand sides built as op(A) X0 is exact)
+    """
+    g = rng(seed)
+    x = np.full(ld * max(order, 1), PAD_AB)
+    if order == 0:
+        return x
+    if dist == "uniform":
+        vals = g.uniform(-1.0, 1.0, (order, order)) / order
+        diag = g.uniform(1.0, 2.0, order) * np.where(g.random(order) < 0.5, -1.0, 1.0)
+    elif dist == "int":
+        vals = g.integers(-4, 5, (order, order)).astype(np.float64)
+        diag = g.choice(np.array([-4.0, -2.0, -1.0, 1.0, 2.0, 4.0]), order)
+    else:
+        raise ValueError(f"unknown distribution {dist!r}")
+    np.fill_diagonal(vals, diag)
+    keep = np.tril(np.ones((order, order), bool)) if uplo in "Ll" else np.triu(np.ones((order, order), bool))
+    if unit:
+        np.fill_diagonal(keep, False)
+    vals[~keep] = PAD_AB
+    x.reshape(order, ld)[:, :order] = vals.T
+    return x

@@ -374,6 +374,129 @@ def served_workload(args, torch, mdg):
     print(json.dumps(out), flush=True)
 
 
+BLAS3_SIZE = 8192
+
+
+def blas3_cpu_baseline(hA, hT, hB, n, budget_s: float):
+    """The oracle's dsyrk, dtrmm and dtrsm on samples of the level-3 problems (host copies):
+    dsyrk on the leading n_s x n_s triangle with the full k, dtrmm and dtrsm on the leading c
+    columns of B (each column is an independent right-hand side) with the full order n. Sample
+    sizes double until each call takes a third of the budget. Returns (TFLOP/s, threads, text)."""
+    import numpy as np
+
+    import oracle
+    threads = oracle.get_threads()
+    share = budget_s / 3
+    total_flops, total_t, parts = 0.0, 0.0, []
+    ns = 64
+    while True:
+        C = np.zeros(ns * ns)
+        t0 = time.perf_counter()
+        assert oracle.dsyrk("L", "N", ns, n, 1.0, hA, n, 0.0, C, ns) == 0
+        dt = time.perf_counter() - t0
+        if dt >= share / 4 or ns >= n:
+            total_flops += float(ns) * (ns + 1) * n
+            total_t += dt
+            parts.append(f"dsyrk L N {ns}x{ns} k={n} ({dt:.1f} s)")
+            break
+        ns *= 2
+    for name in ("dtrmm", "dtrsm"):
+        c = threads
+        while True:
+            Bs = np.ascontiguousarray(hB[: n * c]).copy()
+            t0 = time.perf_counter()
+            assert getattr(oracle, name)("L", "L", "N", "N", n, c, 1.0, hT, n, Bs, n) == 0
+            dt = time.perf_counter() - t0
+            if dt >= share / 4 or c >= n:
+                total_flops += float(n) * n * c
+                total_t += dt
+                parts.append(f"{name} L L N N {n}x{c} ({dt:.1f} s)")
+                break
+            c *= 2
+    return total_flops / total_t / 1e12, threads, "oracle on " + "; ".join(parts)
+
+
+def blas3_workload(args, torch, mdg):
+    """Level-3 operations built on the GEMM, n = 8192: dsyrk (lower, 'N', k = n), dtrmm and
+    dtrsm (side L, lower, 'N', non-unit, m = n). One step = the three calls."""
+    import synth
+    n = BLAS3_SIZE
+    hA = synth.matrix(synth.seed_for(64, 0, 0), n, n, n)
+    hC = synth.matrix(synth.seed_for(64, 0, 2), n, n, n)
+    hT = synth.triangular(synth.seed_for(64, 0, 3), n, n, "L", "uniform")
+    hB = synth.matrix(synth.seed_for(64, 0, 1), n, n, n)
+    dA, dC, dT, dB = (torch.from_numpy(x).cuda() for x in (hA, hC, hT, hB))
+    log("[bench] level-3 operands resident")
+    ops = {
+        "dsyrk": (lambda: mdg.mdg_dsyrk("L", "N", n, n, 1.0, dA, n, 1.0, dC, n), float(n) * (n + 1) * n),
+        "dtrmm": (lambda: mdg.mdg_dtrmm("L", "L", "N", "N", n, n, 1.0, dT, n, dB, n), float(n) * n * n),
+        # solving with the matrix that trmm just multiplied in keeps B bounded step after step
+        "dtrsm": (lambda: mdg.mdg_dtrsm("L", "L", "N", "N", n, n, 1.0, dT, n, dB, n), float(n) * n * n),
+    }
+
+    def step(events=None):
+        for i, (name, (fn, _)) in enumerate(ops.items()):
+            if events is not None:
+                events[i][0].record()
+            st = fn()
+            if st:
+                raise RuntimeError(f"{name}: {mdg.mdg_status_string(st)}")
+            if events is not None:
+                events[i][1].record()
+
+    for w in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {w + 1}/{args.warmup} done")
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in ops] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for s in range(args.steps):
+        step(ev[s])
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    log(f"[bench] {args.steps} timed level-3 steps done in {total_ms:.1f} ms")
+    step_flops = sum(f for _, f in ops.values())
+    value = step_flops * args.steps / (total_ms * 1e-3) / 1e12
+    by_op = {}
+    for i, (name, (_, fl)) in enumerate(ops.items()):
+        ms = sorted(ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps))
+        med = ms[len(ms) // 2]
+        tf = fl / (med * 1e-3) / 1e12
+        by_op[name] = {"ms": round(med, 3), "tflops": round(tf, 2),
+                       "frac_of_peak": round(tf / PEAK_FP64_MFMA_TFLOPS, 4), "flops": fl}
+    # The dsyrk call is one kernel launch: its roofline is that launch's.
+    syrk_ms = by_op["dsyrk"]["ms"]
+    achieved = ops["dsyrk"][1] / (syrk_ms * 1e-3) / 1e12
+    cpu = None
+    if args.cpu_budget > 0:
+        log("[bench] timing the CPU oracle baseline")
+        v, cores, desc = blas3_cpu_baseline(hA, hT, hB, n, args.cpu_budget)
+        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc}
+    vid = mdg.mdg_dsyrk_select_variant("L", "N", n, n)
+    out = {
+        "metric": "FP64 level-3 BLAS on the GEMM (dsyrk + dtrmm + dtrsm) TFLOP/s",
+        "value": round(value, 3), "unit": "TFLOP/s",
+        "pct_of_peak": round(100.0 * value / PEAK_FP64_MFMA_TFLOPS, 1),
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic: seeded Uniform[-1,1] FP64; a well-conditioned triangle (diagonal "
+                "magnitude in [1,2), off-diagonal U[-1,1)/n); resident in HBM before timing",
+        "config": {"workload": f"dsyrk L N n=k={n}; dtrmm and dtrsm L L N N m=n={n}; ld = rows; "
+                               "alpha = beta = 1", "flops_per_step": step_flops, "by_op": by_op},
+        "roofline": {"bound": "mfma", "kernel": f"dsyrk ring kernel ({mdg.mdg_variant_name(vid)}, lower)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "avg_launch_ms": syrk_ms,
+                     "launches": args.steps, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def synth_seed(workload):
     import synth
     return synth.seed_for(workload, 0, 0)
@@ -390,9 +513,11 @@ def main():
     ap.add_argument("--trans", default="", help="comma list of NN,NT,TN,TT (default: all four)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force one kernel variant for every GEMM (default -1: the library's choice)")
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "split", "grouped", "served"],
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "split", "grouped", "served", "blas3"],
                     help="sweep: the native dgemm sweep (default, the headline line); split: the "
-                         "split-precision INT8 path against the native kernel")
+                         "split-precision INT8 path against the native kernel; blas3: dsyrk, "
+                         "dtrmm and dtrsm built on the GEMM")
     ap.add_argument("--split-size", type=int, default=8192)
     ap.add_argument("--tune", action="store_true", help="grouped: run the autotuner first")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
@@ -437,6 +562,9 @@ def main():
         return
     if args.workload == "served":
         served_workload(args, torch, mdg)
+        return
+    if args.workload == "blas3":
+        blas3_workload(args, torch, mdg)
         return
 
     shapes_filter = None

@@ -8,9 +8,9 @@
 //             [T21 T22]        [ 0  T22],
 //
 // so that all but the diagonal blocks' work is GEMM on submatrices, run by mdg_dgemm on the
-// caller's stream. Each diagonal block of order <= kLeaf is finished by one small kernel that
-// keeps the block in LDS and holds one right-hand side (a column of B for side 'L', a row for
-// side 'R') per lane.
+// caller's stream. Each diagonal block of order <= kLeaf is finished by one small kernel in which
+// a wave holds a few right-hand sides (columns of B for side 'L', rows for side 'R'), one element
+// per lane, and the block's rows in registers.
 //
 // Multiply, side 'L', lower op(A):  B2 := alpha T22 B2;  B2 += alpha T21 B1;  B1 := alpha T11 B1.
 // Solve,    side 'L', lower op(A):  X1 from T11 X1 = alpha B1;  B2 := alpha B2 - T21 X1;
@@ -47,80 +47,101 @@ struct LeafArgs {
   int nb, mt, unit;
 };
 
-// Workgroup of 64 lanes; lane w owns vector 64 * blockIdx.x + w. The block of M (the identity
-// outside the nb x nb corner and zero outside the triangle, so the other triangle is never read)
-// and the 64 vectors are staged in LDS with loads along whichever index is contiguous in memory.
+constexpr int kLeafWaves = 4;                            // waves per workgroup
+constexpr int kLeafVecsPerWave = 4;                      // vectors a wave solves side by side
+constexpr int kLeafVecs = kLeafWaves * kLeafVecsPerWave;  // vectors per workgroup
+
+// Entry `lane` (a constant after unrolling) of a wave-wide double, in every lane.
+__device__ __forceinline__ double bcast(double x, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Workgroup of kLeafWaves waves; wave w handles vectors kLeafVecs * blockIdx.x +
+// kLeafVecsPerWave * w + q, q < kLeafVecsPerWave, with lane i holding element i of each. The
+// block of M is staged once per workgroup in LDS (the identity outside the nb x nb corner and
+// zero outside the triangle, so the other triangle is never read), then lane i keeps row i of M
+// in registers. Each of the kLeaf steps broadcasts one entry of every vector to the wave:
+//   solve (column by column):  x_c = y_c / M(c,c);  y_i -= M(i,c) x_c for the rows i after c;
+//   multiply (row sums):       z_i += M(i,c) y_c for the columns c of row i's triangle;
+// so a step is a few wave-wide instructions rather than one lane's serial loop.
 template <bool SOLVE, bool LOWER>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   __shared__ double Ms[kLeaf][kLeaf + 1];
-  __shared__ double Ys[kLeaf][kLeaf + 1];
-  const int lane = threadIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.x * kLeaf;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
 
-  // M: lanes run along the stored index that is contiguous (rows of the stored block).
-  for (int outer = 0; outer < kLeaf; ++outer) {
-    const int i = a.mt ? outer : lane;  // M row
-    const int p = a.mt ? lane : outer;  // M column
+  // Stage M with the stored block's contiguous index running fastest across the threads.
+  for (int e = tid; e < kLeaf * kLeaf; e += kLeafWaves * 64) {
+    const int outer = e / kLeaf, inner = e % kLeaf;
+    const int i = a.mt ? outer : inner;  // M row
+    const int p = a.mt ? inner : outer;  // M column
     const bool in_tri = LOWER ? p <= i : p >= i;
     double x = (i == p) ? 1.0 : 0.0;
     if (i < a.nb && p < a.nb && in_tri && !(i == p && a.unit))
       x = a.mt ? a.A[(int64_t)i * a.lda + p] : a.A[(int64_t)p * a.lda + i];
     Ms[i][p] = x;
   }
-  // The vectors, zero beyond nb elements or beyond the last vector.
-  const bool elem_contig = a.es == 1;
-  for (int outer = 0; outer < kLeaf; ++outer) {
-    const int w = elem_contig ? outer : lane;
-    const int i = elem_contig ? lane : outer;
-    const int64_t v = v0 + w;
-    Ys[w][i] = (v < a.nvec && i < a.nb) ? a.Y[v * a.vs + (int64_t)i * a.es] : 0.0;
-  }
   __syncthreads();
 
-  double y[kLeaf];
+  double mrow[kLeaf];
 #pragma unroll
-  for (int i = 0; i < kLeaf; ++i) y[i] = Ys[lane][i];
+  for (int c = 0; c < kLeaf; ++c) mrow[c] = Ms[lane][c];
+  const double dinv = 1.0 / Ms[lane][lane];  // 1 for a unit diagonal and beyond nb
+
+  const int64_t v0 = ((int64_t)blockIdx.x * kLeafWaves + wave) * kLeafVecsPerWave;
+  const bool row_ok = lane < a.nb;
+  double y[kLeafVecsPerWave];
+#pragma unroll
+  for (int q = 0; q < kLeafVecsPerWave; ++q) {
+    const int64_t v = v0 + q;
+    y[q] = (v < a.nvec && row_ok) ? a.Y[v * a.vs + (int64_t)lane * a.es] : 0.0;
+  }
   const double alpha = a.alpha;
 
   if (SOLVE) {
-    // Substitution in the order the triangle allows: y_i depends on y_p for p before i.
+#pragma unroll
+    for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] = alpha * y[q];
 #pragma unroll
     for (int t = 0; t < kLeaf; ++t) {
-      const int i = LOWER ? t : kLeaf - 1 - t;
-      double s = 0.0;
+      const int c = LOWER ? t : kLeaf - 1 - t;
+      const bool after = LOWER ? lane > c : lane < c;  // rows that still take updates
 #pragma unroll
-      for (int p = LOWER ? 0 : i + 1; p < (LOWER ? i : kLeaf); ++p) s += Ms[i][p] * y[p];
-      const double r = alpha * y[i] - s;
-      y[i] = a.unit ? r : r / Ms[i][i];
+      for (int q = 0; q < kLeafVecsPerWave; ++q) {
+        const double xc = bcast(a.unit ? y[q] : y[q] * dinv, c);
+        y[q] = (lane == c) ? xc : (after ? y[q] - mrow[c] * xc : y[q]);
+      }
     }
   } else {
-    // In place: row i reads y_p on its own side of the diagonal only, so the rows are done in
-    // the order that leaves those entries unchanged until read.
+    double z[kLeafVecsPerWave];
 #pragma unroll
-    for (int t = 0; t < kLeaf; ++t) {
-      const int i = LOWER ? kLeaf - 1 - t : t;
-      double s = 0.0;
+    for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] = 0.0;
 #pragma unroll
-      for (int p = LOWER ? 0 : i; p <= (LOWER ? i : kLeaf - 1); ++p) s += Ms[i][p] * y[p];
-      y[i] = alpha * s;
+    for (int c = 0; c < kLeaf; ++c) {
+      const bool in_tri = LOWER ? c <= lane : c >= lane;
+#pragma unroll
+      for (int q = 0; q < kLeafVecsPerWave; ++q) {
+        const double yc = bcast(y[q], c);
+        z[q] = in_tri ? z[q] + mrow[c] * yc : z[q];
+      }
     }
+#pragma unroll
+    for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] = alpha * z[q];
   }
 
 #pragma unroll
-  for (int i = 0; i < kLeaf; ++i) Ys[lane][i] = y[i];
-  __syncthreads();
-  for (int outer = 0; outer < kLeaf; ++outer) {
-    const int w = elem_contig ? outer : lane;
-    const int i = elem_contig ? lane : outer;
-    const int64_t v = v0 + w;
-    if (v < a.nvec && i < a.nb) a.Y[v * a.vs + (int64_t)i * a.es] = Ys[w][i];
+  for (int q = 0; q < kLeafVecsPerWave; ++q) {
+    const int64_t v = v0 + q;
+    if (v < a.nvec && row_ok) a.Y[v * a.vs + (int64_t)lane * a.es] = y[q];
   }
 }
 
-__global__ void __launch_bounds__(64) leaf_mul_lower(LeafArgs a) { leaf_body<false, true>(a); }
-__global__ void __launch_bounds__(64) leaf_mul_upper(LeafArgs a) { leaf_body<false, false>(a); }
-__global__ void __launch_bounds__(64) leaf_solve_lower(LeafArgs a) { leaf_body<true, true>(a); }
-__global__ void __launch_bounds__(64) leaf_solve_upper(LeafArgs a) { leaf_body<true, false>(a); }
+__global__ void __launch_bounds__(kLeafWaves * 64) leaf_mul_lower(LeafArgs a) { leaf_body<false, true>(a); }
+__global__ void __launch_bounds__(kLeafWaves * 64) leaf_mul_upper(LeafArgs a) { leaf_body<false, false>(a); }
+__global__ void __launch_bounds__(kLeafWaves * 64) leaf_solve_lower(LeafArgs a) { leaf_body<true, true>(a); }
+__global__ void __launch_bounds__(kLeafWaves * 64) leaf_solve_upper(LeafArgs a) { leaf_body<true, false>(a); }
 
 // B := 0 over the logical m x n matrix (the alpha == 0 case; A and B are not read).
 __global__ void __launch_bounds__(256) zero_kernel(int64_t m, int64_t n, double* B, int64_t ldb) {
@@ -281,8 +302,8 @@ int launch_leaf(const Problem& p, const LeafArgs& a, hipStream_t s) {
                                                    : reinterpret_cast<const void*>(&leaf_mul_upper));
   LeafArgs arg = a;
   void* argv[] = {&arg};
-  const int64_t blocks = (a.nvec + kLeaf - 1) / kLeaf;
-  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kLeaf), argv, 0, s);
+  const int64_t blocks = (a.nvec + kLeafVecs - 1) / kLeafVecs;
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kLeafWaves * 64), argv, 0, s);
   if (e != hipSuccess) {
     mdg_record_hip_error((int)e);
     return MDG_ERR_HIP;
@@ -306,7 +327,7 @@ int tri_op(bool solve, char side, char uplo, char transa, char diag, int64_t m, 
   if (!empty && B == nullptr) return 10;
   if (ldb < max1(m)) return 11;
   if (empty) return MDG_SUCCESS;
-  // A leaf launch has one lane per right-hand side: at most INT32_MAX of them.
+  // A leaf launch has one workgroup per kLeafVecs right-hand sides on a 32-bit grid.
   if ((is_left(side) ? n : m) > (int64_t)INT32_MAX) return MDG_ERR_SIZE;
   hipStream_t s = static_cast<hipStream_t>(stream);
 

@@ -50,6 +50,7 @@ struct LeafArgs {
 constexpr int kLeafWaves = 4;                            // waves per workgroup
 constexpr int kLeafVecsPerWave = 4;                      // vectors a wave solves side by side
 constexpr int kLeafVecs = kLeafWaves * kLeafVecsPerWave;  // vectors per workgroup
+static_assert(kLeaf * kLeaf % (kLeafWaves * 64) == 0, "M staging covers the block exactly");
 
 // Entry `lane` (a constant after unrolling) of a wave-wide double, in every lane.
 __device__ __forceinline__ double bcast(double x, int lane) {
@@ -64,7 +65,8 @@ __device__ __forceinline__ double bcast(double x, int lane) {
 // block of M is staged once per workgroup in LDS (the identity outside the nb x nb corner and
 // zero outside the triangle, so the other triangle is never read), then lane i keeps row i of M
 // in registers. Each of the kLeaf steps broadcasts one entry of every vector to the wave:
-//   solve (column by column):  x_c = y_c / M(c,c);  y_i -= M(i,c) x_c for the rows i after c;
+//   solve (column by column, rows pre-scaled to a unit diagonal):
+//                              x_c = y_c;  y_i -= (M(i,c) / M(i,i)) x_c for the rows i after c;
 //   multiply (row sums):       z_i += M(i,c) y_c for the columns c of row i's triangle;
 // so a step is a few wave-wide instructions rather than one lane's serial loop.
 template <bool SOLVE, bool LOWER>
@@ -73,8 +75,11 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
-  // Stage M with the stored block's contiguous index running fastest across the threads.
-  for (int e = tid; e < kLeaf * kLeaf; e += kLeafWaves * 64) {
+  // Stage M with the stored block's contiguous index running fastest across the threads; the
+  // loop is unrolled so that a thread's loads are in flight together.
+#pragma unroll
+  for (int r = 0; r < kLeaf * kLeaf / (kLeafWaves * 64); ++r) {
+    const int e = tid + r * kLeafWaves * 64;
     const int outer = e / kLeaf, inner = e % kLeaf;
     const int i = a.mt ? outer : inner;  // M row
     const int p = a.mt ? inner : outer;  // M column
@@ -89,7 +94,6 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   double mrow[kLeaf];
 #pragma unroll
   for (int c = 0; c < kLeaf; ++c) mrow[c] = Ms[lane][c];
-  const double dinv = 1.0 / Ms[lane][lane];  // 1 for a unit diagonal and beyond nb
 
   const int64_t v0 = ((int64_t)blockIdx.x * kLeafWaves + wave) * kLeafVecsPerWave;
   const bool row_ok = lane < a.nb;
@@ -102,16 +106,22 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   const double alpha = a.alpha;
 
   if (SOLVE) {
+    // M = D U with D its diagonal: solve U y = D^{-1} alpha b, so that each row is scaled once
+    // and a step needs no division (d = 1 for a unit diagonal and beyond nb).
+    const double dinv = 1.0 / Ms[lane][lane];
 #pragma unroll
-    for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] = alpha * y[q];
+    for (int c = 0; c < kLeaf; ++c) mrow[c] *= dinv;
+#pragma unroll
+    for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] = (alpha * y[q]) * dinv;
 #pragma unroll
     for (int t = 0; t < kLeaf; ++t) {
       const int c = LOWER ? t : kLeaf - 1 - t;
-      const bool after = LOWER ? lane > c : lane < c;  // rows that still take updates
+      double xc[kLeafVecsPerWave];
 #pragma unroll
-      for (int q = 0; q < kLeafVecsPerWave; ++q) {
-        const double xc = bcast(a.unit ? y[q] : y[q] * dinv, c);
-        y[q] = (lane == c) ? xc : (after ? y[q] - mrow[c] * xc : y[q]);
+      for (int q = 0; q < kLeafVecsPerWave; ++q) xc[q] = bcast(y[q], c);  // final: unit diagonal
+      if (LOWER ? lane > c : lane < c) {  // the rows that still take updates
+#pragma unroll
+        for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] -= mrow[c] * xc[q];
       }
     }
   } else {
@@ -120,11 +130,15 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
     for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] = 0.0;
 #pragma unroll
     for (int c = 0; c < kLeaf; ++c) {
-      const bool in_tri = LOWER ? c <= lane : c >= lane;
+      double yc[kLeafVecsPerWave];
 #pragma unroll
-      for (int q = 0; q < kLeafVecsPerWave; ++q) {
-        const double yc = bcast(y[q], c);
-        z[q] = in_tri ? z[q] + mrow[c] * yc : z[q];
+      for (int q = 0; q < kLeafVecsPerWave; ++q) yc[q] = bcast(y[q], c);
+      if (LOWER ? c <= lane : c >= lane) {  // column c lies in this row's triangle
+        // Kept as a branch under the lane mask (one mask per step for all vectors) rather than
+        // turned into per-register selects: the empty volatile asm cannot be speculated.
+        __asm__ volatile("");
+#pragma unroll
+        for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] += mrow[c] * yc[q];
       }
     }
 #pragma unroll

@@ -748,37 +748,51 @@ dgemm_ring_kernel(GemmArgs g, int tiles_m, int tiles_n) {
 
 // ------------------------------------------------------------------------------------------------
 // Symmetric rank-k update C := alpha*op(A)*op(A)^T + beta*C on one triangle of C: the GEMM with
-// B = A (transb the opposite of trans) over only the tiles that meet the triangle, each computed
-// by the ring tile with its epilogue masked to the triangle.
+// B = A (transb the opposite of trans) over the tiles that meet the triangle, each computed by
+// the ring tile with its epilogue masked to the triangle.
 //
-// Those tiles are numbered t = 0, 1, ...: for the lower triangle row by row, tile row a holding
-// tile columns 0 .. q(a+1)-1 with q = MT/NT; for the upper triangle column by column, tile column
-// a holding tile rows 0 .. q(a+1)-1 with q = NT/MT (q is 1 or 2). Before line a come
-// P(a) = q a (a+1) / 2 tiles. Only the last line can be cut short by the edge of C, so the count
-// is exact for every earlier line.
+// C is cut into square super-tiles of side S = SR * MT = SC * NT (SR x SC tiles each). The
+// super-tiles on and below the diagonal (for the upper triangle: on and above) are numbered
+// u = 0, 1, ... line by line, line a holding a + 1 of them, so that u < a (a+1)/2 + (a+1) within
+// line a; workgroup t takes tile t % (SR SC) of super-tile t / (SR SC), going down the tile
+// columns. Workgroups on one XCD take consecutive t (as in tile_coords) and so work on one or two
+// super-tiles at a time, which share their SR row panels and SC column panels. Tiles beyond the
+// edge of C or wholly outside the triangle (in the diagonal super-tiles) exit at once.
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void tri_decode(int t, int q, int& a, int& b) {
-  int x = (int)((sqrt(1.0 + 8.0 * (double)t / q) - 1.0) * 0.5);
-  while ((int64_t)q * (x + 1) * (x + 2) / 2 <= t) ++x;  // correct a rounding of the root
-  while (x > 0 && (int64_t)q * x * (x + 1) / 2 > t) --x;
+template <class R>
+struct SyrkGeom {
+  static constexpr int S = 4 * (R::MT > R::NT ? R::MT : R::NT);  // super-tile side
+  static constexpr int SR = S / R::MT, SC = S / R::NT;          // tiles per super-tile side
+  static_assert(S % R::MT == 0 && S % R::NT == 0, "square super-tiles");
+};
+
+__device__ __forceinline__ void tri_decode(int u, int& a, int& b) {
+  int x = (int)((sqrt(1.0 + 8.0 * (double)u) - 1.0) * 0.5);
+  while ((int64_t)(x + 1) * (x + 2) / 2 <= u) ++x;  // correct a rounding of the root
+  while (x > 0 && (int64_t)x * (x + 1) / 2 > u) --x;
   a = x;
-  b = t - q * x * (x + 1) / 2;
+  b = u - x * (x + 1) / 2;
 }
 
 template <class R, bool TA, bool TB, int TRI>
 __global__ void __launch_bounds__(R::THREADS) __attribute__((amdgpu_waves_per_eu(R::MIN_WAVES_PER_EU)))
-dsyrk_ring_kernel(GemmArgs g, int tiles) {
+dsyrk_ring_kernel(GemmArgs g, int wgs) {
   static_assert(TRI == 1 || TRI == 2, "one triangle");
-  constexpr int q = TRI == 1 ? R::MT / R::NT : R::NT / R::MT;
-  static_assert(q >= 1 && (TRI == 1 ? R::MT == q * R::NT : R::NT == q * R::MT),
-                "tile aspect ratio 1 or 2 along the enumerated lines");
+  using G = SyrkGeom<R>;
   __shared__ __attribute__((aligned(16))) double smem[R::LDS_DOUBLES];
   // Contiguous ranges of t per XCD, as in tile_coords (the grid is a multiple of kXcds).
   const int t = (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
-  if (t >= tiles) return;
+  if (t >= wgs) return;
   int a, b;
-  tri_decode(t, q, a, b);
-  ring_tile<R, TA, TB, TRI>(g, TRI == 1 ? a : b, TRI == 1 ? b : a, smem);
+  tri_decode(t / (G::SR * G::SC), a, b);  // super-tile on line a, b-th on it (b <= a)
+  const int r = t % (G::SR * G::SC);
+  const int srow = TRI == 1 ? a : b, scol = TRI == 1 ? b : a;
+  const int tm = srow * G::SR + r % G::SR, tn = scol * G::SC + r / G::SR;
+  const int64_t r0 = (int64_t)tm * R::MT, r1 = r0 + R::MT - 1;  // rows of the tile
+  const int64_t c0 = (int64_t)tn * R::NT, c1 = c0 + R::NT - 1;  // columns of the tile
+  if (r0 >= g.m || c0 >= g.n) return;            // beyond the edge of C
+  if (TRI == 1 ? r1 < c0 : r0 > c1) return;      // wholly outside the triangle
+  ring_tile<R, TA, TB, TRI>(g, tm, tn, smem);
 }
 
 // C := beta*C on one triangle of the n x n C (lower: i >= j, else i <= j); beta == 0 writes zeros
@@ -915,31 +929,30 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-// Ring configurations that run the symmetric rank-k update, per triangle. Each is named by the
-// GEMM variant with the same configuration, whose tile shape, residency and measured
-// efficiencies the choice uses.
+// Ring configurations that run the symmetric rank-k update. Each is named by the GEMM variant
+// with the same configuration, whose tile shape, residency and measured efficiencies the choice
+// uses; each runs either triangle.
 typedef void (*SyrkFn)(GemmArgs, int);
 
 struct SyrkVariant {
   const char* name;  // the variant of kVariants with this ring configuration
-  int tri;           // 1: lower triangle, 2: upper
-  SyrkFn fn[2];      // [trans]: 'N' runs the GEMM case NT, 'T' the case TN
+  int super_side;    // side of the square super-tiles, in elements
+  SyrkFn fn[2][2];   // [trans][upper]: trans 'N' runs the GEMM case NT, 'T' the case TN
 };
 
-template <class R, int TRI>
+template <class R>
 constexpr SyrkVariant make_syrk_variant(const char* name) {
-  return SyrkVariant{name, TRI,
-                     {dsyrk_ring_kernel<R, false, true, TRI>, dsyrk_ring_kernel<R, true, false, TRI>}};
+  return SyrkVariant{name, SyrkGeom<R>::S,
+                     {{dsyrk_ring_kernel<R, false, true, 1>, dsyrk_ring_kernel<R, false, true, 2>},
+                      {dsyrk_ring_kernel<R, true, false, 1>, dsyrk_ring_kernel<R, true, false, 2>}}};
 }
 
 const SyrkVariant kSyrkVariants[] = {
-    make_syrk_variant<Ring256x128t, 1>("ring_f64_256x128x16_w128x32_s3_il"),
-    make_syrk_variant<Ring128x64, 1>("ring_f64_128x64x16_w32x32_s3_il"),
-    make_syrk_variant<Ring128x4i, 1>("ring_f64_128x128x16_w32x32_s4_il"),
-    make_syrk_variant<Ring64s3, 1>("ring_f64_64x64x16_w32x32_s3_il"),
-    make_syrk_variant<Ring128x256wi, 2>("ring_f64_128x256x16_w64x64_s3_il"),
-    make_syrk_variant<Ring128x4i, 2>("ring_f64_128x128x16_w32x32_s4_il"),
-    make_syrk_variant<Ring64s3, 2>("ring_f64_64x64x16_w32x32_s3_il"),
+    make_syrk_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il"),
+    make_syrk_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il"),
+    make_syrk_variant<Ring128x64>("ring_f64_128x64x16_w32x32_s3_il"),
+    make_syrk_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il"),
+    make_syrk_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il"),
 };
 constexpr int kNumSyrkVariants = sizeof(kSyrkVariants) / sizeof(kSyrkVariants[0]);
 
@@ -1156,19 +1169,28 @@ int variant_by_name(const char* name) {
   return -1;
 }
 
-// Tiles of one triangle (1 lower, 2 upper) of an n x n C with mt x nt tiles, counted as the
-// kernel numbers them: q a (a+1) / 2 before the last line a, and that line cut at the edge.
+// Tiles of an n x n C with mt x nt tiles that meet one triangle (1 lower, 2 upper): tile row a
+// of the lower triangle reaches tile column floor(((a+1) mt - 1) / nt), tile column b of the
+// upper one tile row floor(((b+1) nt - 1) / mt), each cut at the edge.
 int64_t syrk_tiles(int tri, int64_t n, int mt, int nt) {
-  const int64_t tiles_m = ceil_div(n, mt), tiles_n = ceil_div(n, nt);
-  const int64_t lines = tri == 1 ? tiles_m : tiles_n, across = tri == 1 ? tiles_n : tiles_m;
-  const int64_t q = tri == 1 ? mt / nt : nt / mt;
-  const int64_t a = lines - 1;
-  const int64_t last = q * (a + 1) < across ? q * (a + 1) : across;
-  return q * a * (a + 1) / 2 + last;
+  const int64_t along = tri == 1 ? mt : nt, across = tri == 1 ? nt : mt;
+  const int64_t lines = ceil_div(n, along), width = ceil_div(n, across);
+  int64_t total = 0;
+  for (int64_t a = 0; a < lines; ++a) {
+    const int64_t last = ((a + 1) * along - 1) / across;
+    total += (last + 1 < width ? last + 1 : width);
+  }
+  return total;
 }
 
-// The entry of kSyrkVariants for triangle `tri` with the smallest estimated time under the GEMM
-// cost model (pick_variant), over the triangle's tiles; `only` >= 0 restricts the choice to the
+// Workgroups of the launch: every tile of the super-tiles on one side of the diagonal.
+int64_t syrk_workgroups(int64_t n, int mt, int nt, int side) {
+  const int64_t lines = ceil_div(n, side);
+  return lines * (lines + 1) / 2 * (side / mt) * (side / nt);
+}
+
+// The entry of kSyrkVariants with the smallest estimated time under the GEMM cost model
+// (pick_variant) over the tiles that meet triangle `tri`; `only` >= 0 restricts the choice to the
 // entry named like kVariants[only]. Returns -1 if none qualifies.
 int pick_syrk(int tri, bool ta, int64_t n, int64_t k, int only) {
   int best = -1;
@@ -1176,7 +1198,6 @@ int pick_syrk(int tri, bool ta, int64_t n, int64_t k, int only) {
   const bool short_k = k <= kShortK;
   for (int s = 0; s < kNumSyrkVariants; ++s) {
     const SyrkVariant& sv = kSyrkVariants[s];
-    if (sv.tri != tri) continue;
     const int vid = variant_by_name(sv.name);
     if (vid < 0 || (only >= 0 && vid != only)) continue;
     const Variant& var = kVariants[vid];
@@ -1362,13 +1383,14 @@ int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, doubl
   const int tri = is_lower(uplo) ? 1 : 2;
 
   int s_idx = -1;
-  int64_t tiles = 0;
+  int64_t wgs = 0;
   if (!no_product) {
     s_idx = pick_syrk(tri, ta, n, k, variant);
     if (s_idx < 0) return MDG_ERR_VARIANT;
-    const Variant& v = kVariants[variant_by_name(kSyrkVariants[s_idx].name)];
-    tiles = syrk_tiles(tri, n, v.mt, v.nt);
-    if (tiles > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;
+    const SyrkVariant& sv = kSyrkVariants[s_idx];
+    const Variant& v = kVariants[variant_by_name(sv.name)];
+    wgs = syrk_workgroups(n, v.mt, v.nt, sv.super_side);
+    if (wgs > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;
     if (!panel_offsets_fit(ta, !ta, v.mt, v.nt, v.kt, n, n, k, lda, lda)) return MDG_ERR_SIZE;
   } else if (variant != MDG_VARIANT_AUTO && pick_syrk(tri, ta, n, 1024, variant) < 0) {
     return MDG_ERR_VARIANT;
@@ -1387,9 +1409,9 @@ int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, doubl
   const int64_t rows_a = ta ? k : n, cols_a = ta ? n : k;
   const int64_t ext = (cols_a - 1) * lda + rows_a;
   GemmArgs g{n, n, k, lda, lda, ldc, alpha, beta, A, A, C, ext, ext};
-  const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;
-  return launch(reinterpret_cast<const void*>(sv.fn[ta ? 1 : 0]), dim3((unsigned)grid),
-                dim3(v.threads), s, g, (int)tiles);
+  const int64_t grid = (wgs + kXcds - 1) / kXcds * kXcds;
+  return launch(reinterpret_cast<const void*>(sv.fn[ta ? 1 : 0][tri == 1 ? 0 : 1]),
+                dim3((unsigned)grid), dim3(v.threads), s, g, (int)wgs);
 }
 
 int mdg_dsyrk(char uplo, char trans, int64_t n, int64_t k, double alpha, const double* A,

@@ -208,7 +208,7 @@ def test_syrk_every_variant(uplo, trans, shape):
     mdg = _mdg()
     accepted = [v for v in [-1] + list(range(mdg.mdg_num_variants())) if _syrk_accepts(v, uplo)]
     names = {mdg.mdg_variant_name(v) for v in accepted if v >= 0}
-    assert len(names) == (4 if uplo == "L" else 3), names
+    assert len(names) == 5, names
     base = 100 * SYRK_SHAPES.index(shape) + 10 * "LU".index(uplo) + 4 * "NT".index(trans)
     for case, (dist, alpha, beta) in enumerate((("int", 1.5, -0.5), ("uniform", -1.25, 0.75),
                                                 ("uniform", 1.0, 0.0))):
@@ -255,15 +255,11 @@ def test_syrk_no_product_and_refusals(uplo):
         assert np.array_equal(g[other].view(np.uint64), C0[other].view(np.uint64))
     st, got = _run_syrk(-1, uplo, "N", n, 4, 0.0, None, lda, 1.0, C, ldc)
     assert st == 0 and np.array_equal(got.view(np.uint64), C.view(np.uint64))
-    # Configurations that cannot run this triangle, and a plain GEMM kernel, are refused.
+    # A GEMM variant without a ring configuration for the update is refused.
     names = [mdg.mdg_variant_name(v) for v in range(mdg.mdg_num_variants())]
-    wide = names.index("ring_f64_128x256x16_w64x64_s3_il")
-    tall = names.index("ring_f64_256x128x16_w128x32_s3_il")
     plain = names.index("mfma_f64_128x128x16_w64x64")
-    bad = tall if uplo == "U" else wide
-    for v in (bad, plain):
-        st, _ = _run_syrk(v, uplo, "N", n, 4, 1.0, A, lda, 0.5, C, ldc)
-        assert st == -2  # MDG_ERR_VARIANT
+    st, _ = _run_syrk(plain, uplo, "N", n, 4, 1.0, A, lda, 0.5, C, ldc)
+    assert st == -2  # MDG_ERR_VARIANT
     assert mdg.mdg_dsyrk("X", "N", n, 4, 1.0, None, lda, 0.5, None, ldc) == 1
     assert mdg.mdg_dsyrk(uplo, "N", n, 4, 1.0, None, n - 1, 0.5, None, ldc) == 6
     assert mdg.mdg_dsyrk(uplo, "T", n, 4, 1.0, to_dev(A), 3, 0.5, None, ldc) == 7

@@ -29,6 +29,7 @@ SKINNY = (8192, 8192, 64)
 TRANS = ["NN", "NT", "TN", "TT"]
 SOURCE = os.path.join(ROOT, "paper_1609_00076_amd", "csrc", "mdg_dgemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+BLAS3_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blas3_traffic.json")
 
 
 def log(msg):
@@ -477,6 +478,16 @@ def blas3_workload(args, torch, mdg):
         v, cores, desc = blas3_cpu_baseline(hA, hT, hB, n, args.cpu_budget)
         cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc}
     vid = mdg.mdg_dsyrk_select_variant("L", "N", n, n)
+    # HBM bytes of the dsyrk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid
+    # only if taken on this kernel source.
+    traffic = None
+    if os.path.exists(BLAS3_TRAFFIC_FILE):
+        try:
+            t = json.load(open(BLAS3_TRAFFIC_FILE))
+            if t.get("source_sha") == source_hash() and t.get("n") == n:
+                traffic = t.get("dsyrk_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
     out = {
         "metric": "FP64 level-3 BLAS on the GEMM (dsyrk + dtrmm + dtrsm) TFLOP/s",
         "value": round(value, 3), "unit": "TFLOP/s",
@@ -491,7 +502,8 @@ def blas3_workload(args, torch, mdg):
         "roofline": {"bound": "mfma", "kernel": f"dsyrk ring kernel ({mdg.mdg_variant_name(vid)}, lower)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "avg_launch_ms": syrk_ms,
-                     "launches": args.steps, "traffic": None},
+                     "launches": args.steps, "traffic": traffic,
+                     "algorithmic_bytes": 8.0 * (n * n + n * (n + 1))},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

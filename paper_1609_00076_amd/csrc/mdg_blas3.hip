@@ -72,6 +72,7 @@ __device__ __forceinline__ double bcast(double x, int lane) {
 template <bool SOLVE, bool LOWER>
 __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   __shared__ double Ms[kLeaf][kLeaf + 1];
+  __shared__ __attribute__((aligned(16))) double Yw[SOLVE ? 1 : kLeafWaves][kLeaf][kLeafVecsPerWave];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
@@ -125,20 +126,42 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
       }
     }
   } else {
+    // Every entry is known before the first step, so the broadcasts come from a copy of the
+    // wave's vectors in LDS (entry c of all of them in one 32-byte row): two uniform reads per
+    // step instead of two readlanes per vector. Only this wave reads its rows, after its own
+    // writes, so no barrier is needed.
+    static_assert(kLeafVecsPerWave == 4, "one 32-byte LDS row per step");
+    double (*yw)[kLeafVecsPerWave] = Yw[wave];
+#pragma unroll
+    for (int q = 0; q < kLeafVecsPerWave; ++q) yw[lane][q] = y[q];
     double z[kLeafVecsPerWave];
 #pragma unroll
     for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] = 0.0;
+    bool finite = true;
 #pragma unroll
-    for (int c = 0; c < kLeaf; ++c) {
-      double yc[kLeafVecsPerWave];
+    for (int q = 0; q < kLeafVecsPerWave; ++q) finite = finite && __builtin_isfinite(y[q]);
+    if (__all(finite)) {
+      // Row i's registers hold zeros outside its triangle, and 0 * y_c is an exact zero for a
+      // finite y_c, so every step can run on all lanes without a mask.
 #pragma unroll
-      for (int q = 0; q < kLeafVecsPerWave; ++q) yc[q] = bcast(y[q], c);
-      if (LOWER ? c <= lane : c >= lane) {  // column c lies in this row's triangle
-        // Kept as a branch under the lane mask (one mask per step for all vectors) rather than
-        // turned into per-register selects: the empty volatile asm cannot be speculated.
-        __asm__ volatile("");
+      for (int c = 0; c < kLeaf; ++c) {
 #pragma unroll
-        for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] += mrow[c] * yc[q];
+        for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] += mrow[c] * yw[c][q];
+      }
+    } else {
+      // An infinity or NaN must reach only the rows whose triangle holds its column.
+#pragma unroll
+      for (int c = 0; c < kLeaf; ++c) {
+        double yc[kLeafVecsPerWave];
+#pragma unroll
+        for (int q = 0; q < kLeafVecsPerWave; ++q) yc[q] = yw[c][q];
+        if (LOWER ? c <= lane : c >= lane) {
+          // Kept as a branch under the lane mask (one mask per step for all vectors) rather
+          // than turned into per-register selects: the empty volatile asm cannot be speculated.
+          __asm__ volatile("");
+#pragma unroll
+          for (int q = 0; q < kLeafVecsPerWave; ++q) z[q] += mrow[c] * yc[q];
+        }
       }
     }
 #pragma unroll

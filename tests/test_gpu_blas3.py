@@ -105,6 +105,25 @@ def test_trmm_uniform(combo, shape):
 
 
 @pytest.mark.parametrize("combo", COMBOS, ids=lambda c: "".join(c))
+def test_trmm_nonfinite_entries(combo):
+    """An infinity and a NaN in B reach exactly the entries the oracle's triangle loops give them
+    to (integer data, so every finite entry is exact as well)."""
+    side, uplo, transa, diag = combo
+    m, n = 130, 70
+    na, A, lda, B, ldb = _tri_case(5, side, uplo, transa, diag, m, n, "int")
+    Bl = synth.view2d(B, m, n, ldb)
+    Bl[3, 5] = np.inf
+    Bl[100, 60] = -np.inf
+    Bl[70, 2] = np.nan
+    ref = B.copy()
+    assert oracle.dtrmm(side, uplo, transa, diag, m, n, 2.0, A, lda, ref, ldb) == 0
+    got = _run_tri("mdg_dtrmm", side, uplo, transa, diag, m, n, 2.0, A, lda, B, ldb)
+    g, r = synth.view2d(got, m, n, ldb), synth.view2d(ref, m, n, ldb)
+    assert np.array_equal(g, r, equal_nan=True)
+    assert np.isfinite(r).sum() > m * n // 2  # most entries stay finite
+
+
+@pytest.mark.parametrize("combo", COMBOS, ids=lambda c: "".join(c))
 @pytest.mark.parametrize("shape", TRI_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
 def test_trsm_integer_exact(combo, shape):
     side, uplo, transa, diag = combo

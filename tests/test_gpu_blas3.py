@@ -338,3 +338,49 @@ def test_tri_full_size_sampled(name):
     else:
         T = _dense_op(A, m, m, "L", "N", "N")
         assert _residual_check("L", m, len(cols), alpha, T, Bs, m, Gs) <= TOL
+
+
+def test_level3_graph_replay_matches_eager():
+    """dsyrk, dtrmm and dtrsm (about two hundred launches each at this size) captured in one
+    graph on torch's stream: every replay, with eager work and synchronizations between replays,
+    gives the eager results bit for bit."""
+    import torch
+    mdg = _mdg()
+    n, k, m = 700, 300, 500
+    hA = synth.matrix(synth.seed_for(65, 0, 0), n, k, n, "uniform")
+    hC = synth.matrix(synth.seed_for(65, 0, 2), n, n, n, "uniform")
+    hT = synth.triangular(synth.seed_for(65, 0, 3), m, m, "U", "uniform")
+    hB = synth.matrix(synth.seed_for(65, 0, 1), m, n, m, "uniform")
+    dA, dC0, dT, dB0 = (to_dev(x) for x in (hA, hC, hT, hB))
+    dC, dB1, dB2 = dC0.clone(), dB0.clone(), dB0.clone()
+
+    def calls():
+        assert mdg.mdg_dsyrk("U", "N", n, k, 0.5, dA, n, 1.5, dC, n) == 0
+        assert mdg.mdg_dtrmm("L", "U", "N", "N", m, n, 1.25, dT, m, dB1, m) == 0
+        assert mdg.mdg_dtrsm("L", "U", "T", "U", m, n, -0.5, dT, m, dB2, m) == 0
+
+    calls()  # eager results (also warms the library's per-device state)
+    torch.cuda.synchronize()
+    want = [x.clone() for x in (dC, dB1, dB2)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # torch's warm-up-before-capture on a side stream
+        for x, x0 in ((dC, dC0), (dB1, dB0), (dB2, dB0)):
+            x.copy_(x0)
+        calls()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    for x, x0 in ((dC, dC0), (dB1, dB0), (dB2, dB0)):
+        x.copy_(x0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        calls()
+    for rep in range(3):
+        for x, x0 in ((dC, dC0), (dB1, dB0), (dB2, dB0)):
+            x.copy_(x0)  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for got, ref in zip((dC, dB1, dB2), want):
+            assert torch.equal(got.view(torch.int64), ref.view(torch.int64)), f"replay {rep}"

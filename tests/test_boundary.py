@@ -147,3 +147,71 @@ def test_sweep_variant_choice():
             assert name(ta, tb, 1024, 1024, 1024).startswith("ring_f64_64x64x16")
             assert name(ta, tb, 2048, 2048, 2048).startswith("ring_f64_128x")
             assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"
+
+
+# ---- level-3 entry points: checks and refusals that return before any HIP call ----------------
+
+FAKE = 0x1000  # a non-NULL address that none of the cases below dereferences
+
+
+def _syrk(uplo="L", trans="N", n=4, k=4, alpha=1.0, A=FAKE, lda=4, beta=0.5, C=FAKE, ldc=4,
+          variant=None):
+    args = (uplo, trans, n, k, alpha, A, lda, beta, C, ldc)
+    return mdg.mdg_dsyrk(*args) if variant is None else mdg.mdg_dsyrk_ex(variant, *args)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(uplo="X"), 1), (dict(trans="Q"), 2), (dict(n=-1), 3), (dict(k=-1), 4),
+    (dict(A=None), 6), (dict(lda=3), 7), (dict(trans="T", n=4, k=8, lda=4), 7),
+    (dict(C=None), 9), (dict(ldc=3), 10), (dict(uplo="X", n=-1), 1),
+])
+def test_dsyrk_argument_codes(kw, code):
+    assert _syrk(**kw) == code
+
+
+def test_dsyrk_quick_returns_and_refusals():
+    assert _syrk(n=0, A=None, C=None, lda=1, ldc=1) == 0
+    assert _syrk(alpha=0.0, beta=1.0, A=None, C=None) == 0
+    assert _syrk(k=0, beta=1.0, A=None, C=None) == 0
+    assert _syrk(variant=mdg.mdg_num_variants()) == -2
+    names = [mdg.mdg_variant_name(v) for v in range(mdg.mdg_num_variants())]
+    assert _syrk(variant=names.index("mfma_f64_128x128x16_w64x64")) == -2  # no ring tile
+    # a k-panel of A would span 4 GiB of 32-bit offsets: refused on the host
+    assert _syrk(n=4, k=100, lda=600_000_000) == -4
+
+
+def test_dsyrk_choice_is_host_logic():
+    vid = mdg.mdg_dsyrk_select_variant("L", "N", 8192, 8192)
+    assert mdg.mdg_variant_name(vid) == "ring_f64_128x64x16_w32x32_s3_il"  # the measured best
+    for uplo, trans in (("U", "N"), ("L", "T"), ("U", "T")):
+        assert mdg.mdg_dsyrk_select_variant(uplo, trans, 8192, 8192) >= 0
+    assert mdg.mdg_dsyrk_select_variant("X", "N", 10, 10) == -2
+    assert mdg.mdg_dsyrk_select_variant("L", "N", -1, 10) == -2
+
+
+def _tri(name, side="L", uplo="L", transa="N", diag="N", m=4, n=4, alpha=1.0, A=FAKE, lda=4,
+         B=FAKE, ldb=4):
+    return getattr(mdg, name)(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb)
+
+
+@pytest.mark.parametrize("name", ["mdg_dtrmm", "mdg_dtrsm"])
+@pytest.mark.parametrize("kw,code", [
+    (dict(side="X"), 1), (dict(uplo="X"), 2), (dict(transa="X"), 3), (dict(diag="X"), 4),
+    (dict(m=-1), 5), (dict(n=-1), 6), (dict(A=None), 8), (dict(lda=3), 9),
+    (dict(side="R", m=4, n=8, lda=4), 9), (dict(side="R", m=8, n=4, lda=4, ldb=8), 0),
+    (dict(B=None), 10), (dict(ldb=3), 11), (dict(side="X", m=-1), 1),
+])
+def test_tri_argument_codes(name, kw, code):
+    if code == 0:
+        # valid arguments would launch kernels: check the same case with m = 0 instead
+        kw = dict(kw, m=0)
+    assert _tri(name, **kw) == code
+
+
+@pytest.mark.parametrize("name", ["mdg_dtrmm", "mdg_dtrsm"])
+def test_tri_plans_are_checked_before_any_launch(name):
+    assert _tri(name, m=0, A=None, B=None) == 0
+    assert _tri(name, n=0, A=None, B=None) == 0
+    # m = 300 needs GEMMs on submatrices; with ldb this large a k-panel of B's 200 columns
+    # would span 4 GiB of 32-bit offsets, so the whole call is refused before anything is enqueued
+    assert _tri(name, m=300, n=200, lda=300, ldb=40_000_000) == -4

@@ -247,27 +247,11 @@ def split_workload(args, torch, mdg):
     print(json.dumps(out), flush=True)
 
 
-GROUPED_SIGNATURE = "grouped|2048|mnk~logU[16,512]|trans iid|tight ld"
-
-
 def grouped_problems(count=2048, lo=16, hi=512, seed_variant=0):
     """Workload of 2048 independent GEMMs: m, n, k log-uniform integers in [lo, hi], transposes
     iid, alpha and beta ~ U[-1, 1), tight leading dimensions, entries U[-1, 1)."""
     import synth
-    g = synth.rng(synth.seed_for(4, seed_variant, 9))
-    m = synth.log_uniform_int(g, lo, hi, count)
-    n = synth.log_uniform_int(g, lo, hi, count)
-    k = synth.log_uniform_int(g, lo, hi, count)
-    ta = g.integers(0, 2, count)
-    tb = g.integers(0, 2, count)
-    ab = g.uniform(-1.0, 1.0, (count, 2))
-    probs = []
-    for i in range(count):
-        p = synth.problem(4, seed_variant * 10000 + i, "NT"[ta[i]], "NT"[tb[i]], int(m[i]),
-                          int(n[i]), int(k[i]), ld_rule=synth.ld_tight)
-        p["alpha"], p["beta"] = float(ab[i, 0]), float(ab[i, 1])
-        probs.append(p)
-    return probs
+    return synth.grouped_batch(count, lo, hi, seed_variant)
 
 
 def grouped_workload(args, torch, mdg):
@@ -287,10 +271,10 @@ def grouped_workload(args, torch, mdg):
     total_bytes = sum(8.0 * (g["m"] * g["k"] + g["k"] * g["n"] + 2 * g["m"] * g["n"]) for g in gemms)
     db = args.tune_db or tuner.DB_PATH
     if args.tune:
-        entry = tuner.tune_grouped(gemms, GROUPED_SIGNATURE, db_path=db, log=log)
+        entry = tuner.tune_grouped(gemms, tuner.GROUPED_SIGNATURE, db_path=db, log=log)
         policy = entry["policy"]
     else:
-        policy = tuner.best_policy(GROUPED_SIGNATURE, db_path=db)
+        policy = tuner.best_policy(tuner.GROUPED_SIGNATURE, db_path=db)
     log(f"[bench] policy {policy}")
 
     def timed(fn, reps):

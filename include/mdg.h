@@ -121,7 +121,9 @@ const char *mdg_status_string(int status);
  * [-phi, phi]: at k = 8192, nslices = 7 (phi = 0), 8 (phi = 8), 10 (phi = 32) keep
  * max |C - Cref| / (|A||B|)_ij below 1e-13; at k as small as 32, phi = 8 needs 9, and phi = 32 is
  * not reached even with 12 (a short row spanning 2^64 leaves (|A||B|)_ij far below the product of
- * the maxima). Inputs must be finite: NaN or Inf in A or B gives an unspecified result.
+ * the maxima). Non-finite inputs: a row of op(A) (column of op(B)) holding NaN or Inf makes that
+ * whole row (column) of C NaN -- where IEEE arithmetic would give NaN or +-Inf there, the split
+ * path gives NaN; NaN in the old C propagates through beta*C as usual.
  * ------------------------------------------------------------------------------------------ */
 
 /* Largest supported `nslices` (the smallest is 1). */
@@ -159,7 +161,8 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
  * for r < rp, p < kp (zero for r >= rows or p >= k): each 32-deep k-panel of a slice is rp*32
  * bytes, made of 1 KiB chunks of 32 rows in which row i keeps its two 16-byte halves at slots
  * slot(i, 0) and slot(i, 1). `slices` holds nslices*rp*kp bytes; and exponents[r] = e with
- * max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row). Returns 0, or
+ * max_p |x(r,p)| = f * 2^e, f in [0.5, 1) (0 for a zero row; 0x7FFFFFFF for a row holding NaN or
+ * Inf, whose slices are then unspecified). Returns 0, or
  * 1 operand, 2 trans, 3 rows < 0, 4 k < 0, 5 X NULL, 6 ld too small, 7 nslices out of range,
  * 8 output NULL, or a negative runtime code.
  */

@@ -20,6 +20,10 @@ _lib = None
 
 MDG_SCHEDULE_NATURAL = 0
 MDG_SCHEDULE_LPT = 1
+MDG_ERR_HIP = -1
+MDG_ERR_VARIANT = -2
+MDG_ERR_DEVICE = -3
+MDG_ERR_SIZE = -4
 
 
 class mdg_gemm_desc(ctypes.Structure):

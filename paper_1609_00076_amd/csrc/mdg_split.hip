@@ -7,13 +7,15 @@
 //      2024);
 //   2. split each scaled entry x into S int8 slices q_1..q_S, x = sum_s q_s 2^-7s + r 2^-7S,
 //      by S exact binary64 steps (x := 128x, q := trunc(x), x := x - q);
-//   3. form the slice products P_st = A_s B_t with s + t <= S + 1 exactly in INT32 on
-//      v_mfma_i32_16x16x64_i8, summed per anti-diagonal d = s + t;
+//   3. form the slice products P_st = A_s B_t with s + t <= S + 1 exactly in INT32, summed per
+//      anti-diagonal d = s + t: up to 8 slices on v_mfma_i32_32x32x32_i8 (128x64 tiles, 32-deep
+//      k-steps), for 9 and 10 slices on v_mfma_i32_16x16x64_i8 (64x64 tiles, 64-deep k-steps);
 //   4. recombine in binary64: C' = sum_d 2^-7d sum_{s+t=d} P_st, unscale by 2^(e_i + f_j), and
 //      apply alpha and beta in binary64.
-// Slices live in a caller-provided workspace as 64-row x 64-k tiles of bytes (each row of op(A),
-// each column of op(B), holds 64 consecutive k in one 64-byte run), padded with zeros to multiples
-// of 64 in rows and in k.
+// A row of op(A) or column of op(B) holding NaN or Inf is flagged by the exponent pass, and the
+// epilogue writes NaN to its row or column of C (the product there is not finite).
+// Slices live in the caller's workspace as 32-deep k-panels of 1 KiB chunks of 32 rows (slice_offset), padded
+// with zeros to multiples of 128 rows and 64 k-values.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -88,12 +90,30 @@ __device__ __forceinline__ void slice16(double (&v)[16], v4i (&q)[S]) {
 // Exponents are gathered in two passes. Pass 1 (split_max_kernel) takes the maximum magnitude of
 // each row over a chunk of k and merges the chunks with an integer atomicMax on the encoded
 // exponent enc = e + kExpBias (frexp's exponent is monotonic in the magnitude; 0 = no non-zero
-// entry yet, so the array starts zeroed). Pass 2 (split_tile_kernel) decodes it. NaN entries are
-// skipped by the maximum, as fmax does.
+// entry yet, so the array starts zeroed). Pass 2 (split_tile_kernel) decodes it.
 constexpr int kExpBias = 2048;  // above the magnitude of any binary64 exponent
 constexpr int kMaxChunk = 512;  // k per workgroup in pass 1
 
+// A row (column) holding NaN or Inf is marked by kNonFinite, which exceeds every encoded
+// exponent, so the atomic maximum keeps it; the exponent-only entry point reports it as
+// kNonFiniteExp.
+constexpr int kNonFinite = 4 * kExpBias;
+constexpr int kNonFiniteExp = 0x7FFFFFFF;
+
 __device__ __forceinline__ int decode_exponent(int enc) { return enc ? enc - kExpBias : 0; }
+
+// Magnitude for the row maximum: NaN and Inf count as Inf (fmax alone would skip a NaN).
+__device__ __forceinline__ double max_key(double x) {
+  const double a = fabs(x);
+  return a <= 1.7976931348623157e308 ? a : __builtin_inf();
+}
+
+// alpha-free recombined product of row i and column j: cf * 2^(e_i + f_j), or NaN when either
+// operand line holds a non-finite entry.
+__device__ __forceinline__ double unscale(double cf, int enc_a, int enc_b) {
+  if (enc_a == kNonFinite || enc_b == kNonFinite) return __builtin_nan("");
+  return ldexp(cf, decode_exponent(enc_a) + decode_exponent(enc_b));
+}
 
 __global__ void __launch_bounds__(256) zero_i32_kernel(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -102,7 +122,7 @@ __global__ void __launch_bounds__(256) zero_i32_kernel(int32_t* p, int64_t n) {
 
 __global__ void __launch_bounds__(256) decode_exponents_kernel(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    p[i] = decode_exponent(p[i]);
+    p[i] = p[i] == kNonFinite ? kNonFiniteExp : decode_exponent(p[i]);
 }
 
 // Pass 1 over a 64-row block and a kMaxChunk-deep chunk of k; one thread per row (of the 64),
@@ -119,7 +139,7 @@ __global__ void __launch_bounds__(256) split_max_kernel(const double* X, int64_t
   if (!ROW_CONTIG) {
     const int r = t & 63;
     if (row0 + r < rows)
-      for (int64_t p = p0 + (t >> 6); p < p1; p += 4) mx = fmax(mx, fabs(X[p * ld + row0 + r]));
+      for (int64_t p = p0 + (t >> 6); p < p1; p += 4) mx = fmax(mx, max_key(X[p * ld + row0 + r]));
     red[t >> 6][r] = mx;
   } else {
     // wave w takes rows w, w+4, ...; its lanes read 64 consecutive k of a row
@@ -127,7 +147,7 @@ __global__ void __launch_bounds__(256) split_max_kernel(const double* X, int64_t
     for (int rr = w; rr < 64; rr += 4) {
       double m2 = 0.0;
       if (row0 + rr < rows)
-        for (int64_t p = p0 + lane; p < p1; p += 64) m2 = fmax(m2, fabs(X[(row0 + rr) * ld + p]));
+        for (int64_t p = p0 + lane; p < p1; p += 64) m2 = fmax(m2, max_key(X[(row0 + rr) * ld + p]));
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) m2 = fmax(m2, __shfl_xor(m2, off, 64));
       if (lane == 0) red[0][rr] = m2;
@@ -137,7 +157,8 @@ __global__ void __launch_bounds__(256) split_max_kernel(const double* X, int64_t
   __syncthreads();
   if (t < 64 && row0 + t < rows) {
     const double m = fmax(fmax(red[0][t], red[1][t]), fmax(red[2][t], red[3][t]));
-    if (m != 0.0) atomicMax(enc + row0 + t, row_exponent(m) + kExpBias);
+    if (m != 0.0)
+      atomicMax(enc + row0 + t, m == __builtin_inf() ? kNonFinite : row_exponent(m) + kExpBias);
   }
 }
 
@@ -170,7 +191,8 @@ __global__ void __launch_bounds__(256) split_tile_kernel(const double* X, int64_
   }
   __syncthreads();
   const int r = t >> 2, q0 = 16 * (t & 3);
-  const int e = (row0 + r < rows) ? decode_exponent(enc[row0 + r]) : 0;
+  const int enc_r = (row0 + r < rows) ? enc[row0 + r] : 0;
+  const int e = enc_r == kNonFinite ? 0 : decode_exponent(enc_r);  // such rows' slices are unused
   double v[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) v[i] = ldexp(tile[r][q0 + i], -e);
@@ -384,13 +406,13 @@ split_gemm_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   for (int bi = 0; bi < kRB; ++bi) {
     const int64_t i = row0 + wave_m * 32 + 16 * bi + l16;
     if (i >= g.m) continue;
-    const int ei = decode_exponent(g.ea[i]);
+    const int enc_i = g.ea[i];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t j = col0 + wave_n * 16 + 4 * lq + r;
       if (j >= g.n) continue;
       double* c = g.C + j * g.ldc + i;
-      const double v = alpha * ldexp(cf[bi][r], ei + decode_exponent(g.eb[j]));
+      const double v = alpha * unscale(cf[bi][r], enc_i, g.eb[j]);
       *c = (beta != 0.0) ? v + beta * *c : v;
     }
   }
@@ -614,14 +636,14 @@ __device__ __forceinline__ void split32_tile(const SplitArgs& g, int tiles_m, in
   // Epilogue: C(i,j) := alpha * 2^(e_i + f_j) * C'(i,j) + beta * C(i,j).
   const int64_t i = row0 + 32 * wave_m + (lane & 31);
   if (i >= g.m) return;
-  const int ei = decode_exponent(g.ea[i]);
+  const int enc_i = g.ea[i];
   const double alpha = g.alpha, beta = g.beta;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int64_t j = col0 + 32 * wave_n + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (j >= g.n) continue;
     double* c = g.C + j * g.ldc + i;
-    const double v = alpha * ldexp(cf[r], ei + decode_exponent(g.eb[j]));
+    const double v = alpha * unscale(cf[r], enc_i, g.eb[j]);
     *c = (beta != 0.0) ? v + beta * *c : v;
   }
 }
@@ -717,6 +739,72 @@ int launch_fill(const void* fn, int32_t* p, int64_t n, hipStream_t s) {
   return launch(fn, dim3((unsigned)blocks), dim3(256), s, argv);
 }
 
+// Checks of the split entry points' arguments 1-14, in dgemm order (the slice count is 14).
+int split_check(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                const double* C, int64_t ldc, int nslices) {
+  if (!is_notrans(transa) && !is_trans(transa)) return 1;
+  if (!is_notrans(transb) && !is_trans(transb)) return 2;
+  if (m < 0) return 3;
+  if (n < 0) return 4;
+  if (k < 0) return 5;
+  const bool empty = (m == 0 || n == 0);
+  const bool no_product = (alpha == 0.0 || k == 0);
+  const bool reads_ab = !empty && !no_product;
+  const int64_t rows_a = is_notrans(transa) ? m : k;
+  const int64_t rows_b = is_notrans(transb) ? k : n;
+  if (reads_ab && A == nullptr) return 7;
+  if (lda < max1(rows_a)) return 8;
+  if (reads_ab && B == nullptr) return 9;
+  if (ldb < max1(rows_b)) return 10;
+  if (!empty && !(no_product && beta == 1.0) && C == nullptr) return 12;
+  if (ldc < max1(m)) return 13;
+  if (nslices < 1 || nslices > kMaxSlices) return 14;
+  return MDG_SUCCESS;
+}
+
+// Limits of one launch: slice offsets are 32-bit, and the tile count must fit the grid.
+int split_size_check(int64_t m, int64_t n, int nslices, const Layout& L) {
+  if (L.a_bytes > (int64_t)0xFFFFFFFF - 4096 || L.b_bytes > (int64_t)0xFFFFFFFF - 4096)
+    return MDG_ERR_SIZE;
+  const Fns& f = kFns[nslices];
+  const int64_t tiles_m = (m + f.mt - 1) / f.mt, tiles_n = (n + f.nt - 1) / f.nt;
+  if (tiles_m * tiles_n > (int64_t)INT32_MAX / 256) return MDG_ERR_SIZE;
+  return MDG_SUCCESS;
+}
+
+// The whole split computation on checked arguments, with the workspace `ws` laid out as L. Clears
+// the exponent arrays with a kernel (no memset), then slices both operands and runs the GEMM.
+int split_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, int nslices, int8_t* ws, const Layout& L, hipStream_t s) {
+  const Fns& f = kFns[nslices];
+  const int64_t tiles_m = (m + f.mt - 1) / f.mt, tiles_n = (n + f.nt - 1) / f.nt;
+  int8_t* as = ws;
+  int8_t* bs = ws + L.a_bytes;
+  int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
+  int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
+  // ea and eb are adjacent: zero both encoded exponent arrays in one launch
+  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), ea,
+                       (L.total - L.ea_off) / 4, s);
+  if (st) return st;
+  st = launch_slices(f, is_trans(transa), A, lda, m, k, L.kp, as, ea, s);
+  if (st) return st;
+  st = launch_slices(f, is_notrans(transb), B, ldb, n, k, L.kp, bs, eb, s);
+  if (st) return st;
+
+  // INT32 headroom: a diagonal sums at most nslices products of f.kstep terms of magnitude
+  // <= 127^2 per k-step.
+  const int64_t per_step = (int64_t)nslices * f.kstep * kSliceMax * kSliceMax;
+  int flush = (int)((int64_t)INT32_MAX / per_step);
+  if (flush < 1) flush = 1;
+  SplitArgs g{m, n, L.kp, alpha, beta, C, ldc, as, bs, ea, eb, flush};
+  int tm = (int)tiles_m, tn = (int)tiles_n;
+  void* argv[] = {&g, &tm, &tn};
+  return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)((tiles_m * tiles_n + 7) / 8 * 8)),
+                dim3(kThreads), s, argv);  // both GEMM kernels run kThreads threads
+}
+
 }  // namespace mdg_split_impl
 
 using namespace mdg_split_impl;
@@ -744,8 +832,10 @@ int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const dou
   if (nslices < 1 || nslices > kMaxSlices) return 7;
   if (rows > 0 && (slices == nullptr || exponents == nullptr)) return 8;
   if (rows == 0) return MDG_SUCCESS;
+  int st = mdg_device_check();
+  if (st) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), exponents, rows, s);
+  st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), exponents, rows, s);
   if (st) return st;
   st = launch_slices(kFns[nslices], row_contig, X, ld, rows, k, kpad(k), slices, exponents, s);
   if (st) return st;
@@ -756,60 +846,21 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                     double* C, int64_t ldc, int nslices, void* workspace, int64_t workspace_bytes,
                     void* stream) {
-  if (!is_notrans(transa) && !is_trans(transa)) return 1;
-  if (!is_notrans(transb) && !is_trans(transb)) return 2;
-  if (m < 0) return 3;
-  if (n < 0) return 4;
-  if (k < 0) return 5;
-  const bool empty = (m == 0 || n == 0);
+  int st = split_check(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices);
+  if (st) return st;
   const bool no_product = (alpha == 0.0 || k == 0);
-  const bool reads_ab = !empty && !no_product;
-  const int64_t rows_a = is_notrans(transa) ? m : k;
-  const int64_t rows_b = is_notrans(transb) ? k : n;
-  if (reads_ab && A == nullptr) return 7;
-  if (lda < max1(rows_a)) return 8;
-  if (reads_ab && B == nullptr) return 9;
-  if (ldb < max1(rows_b)) return 10;
-  if (!empty && !(no_product && beta == 1.0) && C == nullptr) return 12;
-  if (ldc < max1(m)) return 13;
-  if (nslices < 1 || nslices > kMaxSlices) return 14;
-  if (empty || (no_product && beta == 1.0)) return MDG_SUCCESS;
+  if (m == 0 || n == 0 || (no_product && beta == 1.0)) return MDG_SUCCESS;
   if (no_product)  // C := beta*C needs no slices: the native entry point does exactly this
     return mdg_dgemm(transa, transb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, stream);
   const Layout L = layout(m, n, k, nslices);
   if (workspace == nullptr || workspace_bytes < L.total) return 15;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return 15;
-  if (L.a_bytes > (int64_t)0xFFFFFFFF - 4096 || L.b_bytes > (int64_t)0xFFFFFFFF - 4096)
-    return MDG_ERR_SIZE;  // slice offsets are 32-bit
-  const Fns& f = kFns[nslices];
-  const int64_t tiles_m = (m + f.mt - 1) / f.mt, tiles_n = (n + f.nt - 1) / f.nt;
-  if (tiles_m * tiles_n > (int64_t)INT32_MAX / 256) return MDG_ERR_SIZE;
-
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int8_t* ws = static_cast<int8_t*>(workspace);
-  int8_t* as = ws;
-  int8_t* bs = ws + L.a_bytes;
-  int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
-  int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
-  // ea and eb are adjacent: zero both encoded exponent arrays in one launch
-  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), ea,
-                       (L.total - L.ea_off) / 4, s);
+  st = split_size_check(m, n, nslices, L);
   if (st) return st;
-  st = launch_slices(f, is_trans(transa), A, lda, m, k, L.kp, as, ea, s);
+  st = mdg_device_check();
   if (st) return st;
-  st = launch_slices(f, is_notrans(transb), B, ldb, n, k, L.kp, bs, eb, s);
-  if (st) return st;
-
-  // INT32 headroom: a diagonal sums at most nslices products of f.kstep terms of magnitude
-  // <= 127^2 per k-step.
-  const int64_t per_step = (int64_t)nslices * f.kstep * kSliceMax * kSliceMax;
-  int flush = (int)((int64_t)INT32_MAX / per_step);
-  if (flush < 1) flush = 1;
-  SplitArgs g{m, n, L.kp, alpha, beta, C, ldc, as, bs, ea, eb, flush};
-  int tm = (int)tiles_m, tn = (int)tiles_n;
-  void* argv[] = {&g, &tm, &tn};
-  return launch(reinterpret_cast<const void*>(f.gemm), dim3((unsigned)((tiles_m * tiles_n + 7) / 8 * 8)),
-                dim3(kThreads), s, argv);  // both GEMM kernels run kThreads threads
+  return split_run(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices,
+                   static_cast<int8_t*>(workspace), L, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

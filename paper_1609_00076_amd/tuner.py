@@ -20,6 +20,8 @@ THRESHOLDS = (0, 40, 64, 96, 160, 1 << 30)
 SCHEDULES = (b.MDG_SCHEDULE_NATURAL, b.MDG_SCHEDULE_LPT)
 GRIDS = (256, 512, 1024, 2048)
 DEFAULT_POLICY = {"threshold": 48, "schedule": b.MDG_SCHEDULE_LPT, "grid": 1024}
+# Signature of the batched workload: 2048 GEMMs, m, n, k log-uniform in [16, 512].
+GROUPED_SIGNATURE = "grouped|2048|mnk~logU[16,512]|trans iid|tight ld"
 
 
 def classes_for(gemms, threshold):

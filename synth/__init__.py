@@ -157,3 +157,28 @@ def triangular(seed: int, order: int, ld: int, uplo: str, dist: str = "uniform",
     vals[~keep] = PAD_AB
     x.reshape(order, ld)[:, :order] = vals.T
     return x
+
+
+def grouped_batch(count: int = 2048, lo: int = 16, hi: int = 512, seed_variant: int = 0,
+                  dist: str = "uniform"):
+    """The batched workload: `count` independent GEMMs whose m, n, k are log-uniform integers in
+    [lo, hi], transposes iid, alpha and beta ~ U[-1, 1), tight leading dimensions and entries
+    drawn from `dist`. Returns a list of problem dicts (as `problem`) with alpha and beta added.
+    With dist="int" the scalars are rounded to multiples of 0.5 so every result stays exact."""
+    g = rng(seed_for(4, seed_variant, 9))
+    m = log_uniform_int(g, lo, hi, count)
+    n = log_uniform_int(g, lo, hi, count)
+    k = log_uniform_int(g, lo, hi, count)
+    ta = g.integers(0, 2, count)
+    tb = g.integers(0, 2, count)
+    ab = g.uniform(-1.0, 1.0, (count, 2))
+    probs = []
+    for i in range(count):
+        p = problem(4, seed_variant * 10000 + i, "NT"[ta[i]], "NT"[tb[i]], int(m[i]), int(n[i]),
+                    int(k[i]), ld_rule=ld_tight, dist=dist)
+        alpha, beta = float(ab[i, 0]), float(ab[i, 1])
+        if dist == "int":
+            alpha, beta = float(np.round(alpha * 4) / 2), float(np.round(beta * 4) / 2)
+        p["alpha"], p["beta"] = alpha, beta
+        probs.append(p)
+    return probs

@@ -215,3 +215,18 @@ def test_tri_plans_are_checked_before_any_launch(name):
     # m = 300 needs GEMMs on submatrices; with ldb this large a k-panel of B's 200 columns
     # would span 4 GiB of 32-bit offsets, so the whole call is refused before anything is enqueued
     assert _tri(name, m=300, n=200, lda=300, ldb=40_000_000) == -4
+
+
+def test_split_entry_points_check_the_device_after_the_arguments():
+    """Argument and size checks come first; then, before any launch, the device check (on this
+    CPU-only host it fails with a runtime code rather than launching)."""
+    fake = 1 << 40
+    need = mdg.mdg_dgemm_split_workspace_size(64, 64, 64, 7)
+    st = mdg.mdg_dgemm_split("N", "N", 64, 64, 64, 1.0, fake, 64, fake, 64, 0.0, fake, 64, 7,
+                             fake, need)
+    assert st in (mdg.MDG_ERR_HIP, mdg.MDG_ERR_DEVICE)
+    assert mdg.mdg_dgemm_split("N", "N", 64, 64, 64, 1.0, fake, 64, fake, 64, 0.0, fake, 64, 7,
+                               fake, need - 1) == 15
+    st = mdg.mdg_split_slices(0, "N", 64, 64, fake, 64, 7, fake, fake)
+    assert st in (mdg.MDG_ERR_HIP, mdg.MDG_ERR_DEVICE)
+    assert mdg.mdg_split_slices(0, "N", 64, 64, fake, 63, 7, fake, fake) == 6

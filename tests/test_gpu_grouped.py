@@ -145,3 +145,49 @@ def test_graph_replays():
         graph.replay()
         torch.cuda.synchronize()
         _check_against_oracle(probs, gemms, exact=False)
+
+
+def test_full_batch_graph_replays_match_oracle():
+    """The benchmark's batch itself: 2048 GEMMs with m, n, k log-uniform in [16, 512], random
+    transposes and scalars, tight leading dimensions, under the tuned policy. One grouped launch is
+    captured in a graph and replayed twice (C reset between replays), on the tuned grid and on the
+    default grid (where each workgroup walks several tiles); every GEMM is compared with the
+    oracle element by element at 1e-13 of D, and its C padding must stay untouched."""
+    import torch
+    from paper_1609_00076_amd import tuner
+    from paper_1609_00076_amd.grouped import GroupedPlan
+    probs = synth.grouped_batch()
+    assert len(probs) == 2048
+    refs = [run_oracle(p, p["alpha"], p["beta"]) for p in probs]
+    gemms = _to_device(probs)
+    c0 = [g["C"].clone() for g in gemms]
+    policy = tuner.best_policy(tuner.GROUPED_SIGNATURE)
+    classes = tuner.classes_for(gemms, policy["threshold"])
+    for grid in (policy["grid"], 0):
+        plan = GroupedPlan(gemms, classes, policy["schedule"])
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.launch(grid)  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.launch(grid)
+        for replay in range(2):
+            for g, c in zip(gemms, c0):
+                g["C"].copy_(c)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            print(f"[grouped] 2048-GEMM batch, grid {grid}, replay {replay}: checking",
+                  flush=True)
+            worst = 0.0
+            for i, (p, g, (ref, D)) in enumerate(zip(probs, gemms, refs)):
+                got = g["C"].cpu().numpy()
+                m, n, ldc = p["m"], p["n"], p["ldc"]
+                e = rel_err(logical(got, m, n, ldc).T, logical(ref, m, n, ldc).T, D)
+                worst = max(worst, e)
+                assert e <= TOL, f"GEMM {i} {p['transa']}{p['transb']} {m}x{n}x{p['k']}: {e:.2e}"
+                if ldc > m:
+                    assert np.all(got.view(np.uint64).reshape(n, ldc)[:, m:] == synth.PAD_C_BITS)
+            print(f"[grouped] worst error {worst:.2e}", flush=True)

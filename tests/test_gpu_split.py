@@ -111,6 +111,48 @@ def test_slice_products_match_reference_bitwise(shape, trans, S):
     assert same_bits(got, want)
 
 
+@pytest.mark.parametrize("S,phi", [(7, 0), (9, 8)])
+@pytest.mark.parametrize("trans", ["NN", "TT"])
+def test_non_finite_inputs_poison_only_their_row_and_column(S, phi, trans):
+    """A NaN in op(A) and an Inf in op(B): the oracle's C is non-finite exactly on that row of C
+    and that column of C; the split path gives NaN there and the oracle's values (to 1e-13 of D)
+    everywhere else. The exponent-only entry point flags both lines."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    ta, tb = trans
+    m, n, k = 150, 90, 200
+    p = synth.problem(36, S, ta, tb, m, n, k, ld_rule=_pad3, dist="scaled" if phi else "uniform",
+                      phi=phi)
+    ia, pa, jb, pb = 37, 11, 61, 150
+    opa = _op(p["A"], ta, m, k, p["lda"])
+    opb = _op(p["B"], tb, k, n, p["ldb"])
+    opa[ia, pa] = np.nan    # a view into p["A"]'s storage
+    opb[pb, jb] = np.inf
+    got = logical(_run_split(p, 1.0, 0.5, S), m, n, p["ldc"])
+    ref_full, D = run_oracle(p, 1.0, 0.5)
+    ref = logical(ref_full, m, n, p["ldc"])
+    bad = ~np.isfinite(ref)
+    expect_bad = np.zeros((m, n), bool)
+    expect_bad[ia, :] = True
+    expect_bad[:, jb] = True
+    assert np.array_equal(bad, expect_bad), "the oracle's non-finite pattern (a pin of the test)"
+    assert np.all(np.isnan(got[bad]))
+    Dm = D.reshape(n, m).T
+    assert rel_err(got[~bad], ref[~bad], Dm[~bad]) <= TOL
+    # the slicing entry point reports both lines as non-finite
+    for operand, trans_x, X, ld, rows, line in ((0, ta, p["A"], p["lda"], m, ia),
+                                                 (1, tb, p["B"], p["ldb"], n, jb)):
+        dX = torch.from_numpy(X).cuda()
+        kp = (k + 63) // 64 * 64
+        rp = (rows + 127) // 128 * 128
+        sl = torch.empty(S * rp * kp, dtype=torch.int8, device="cuda")
+        ex = torch.empty(rows, dtype=torch.int32, device="cuda")
+        assert mdg.mdg_split_slices(operand, trans_x, rows, k, dX, ld, S, sl, ex) == 0
+        torch.cuda.synchronize()
+        e = ex.cpu().numpy()
+        assert e[line] == 0x7FFFFFFF and np.all(np.delete(e, line) < 64)
+
+
 @pytest.mark.parametrize("phi,S", [(0, 7), (8, 8), (32, 10)])
 @pytest.mark.parametrize("trans", TRANS)
 def test_against_fp64_oracle(trans, phi, S):
@@ -193,4 +235,28 @@ def test_8192_sampled(phi, S):
     ref_r, d_r, ref_c, d_c = sampled_reference(p, 1.0, 1.0, R, Sx)
     er, ec = rel_err(got_rows, ref_r, d_r), rel_err(got_cols, ref_c, d_c)
     print(f"[split] phi={phi} S={S} row err {er:.2e} col err {ec:.2e}", flush=True)
+    assert er <= TOL and ec <= TOL
+
+
+@pytest.mark.parametrize("S,trans", [(9, "TN"), (10, "NT")])
+def test_wide_slice_kernel_at_size(S, trans):
+    """The 64x64-tile kernel that runs 9 and 10 slices (the served stream's phi = 8 requests use
+    9), at a ragged size near the top of the served range, on sampled full rows and columns."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    m, n, k = 2500, 1900, 3100
+    p = synth.problem(37, S, trans[0], trans[1], m, n, k, ld_rule=_pad3, dist="scaled", phi=8)
+    print(f"[split] {trans} {m}x{n}x{k} S={S}", flush=True)
+    dA, dB, dC = (torch.from_numpy(p[x]).cuda() for x in "ABC")
+    ws_bytes = mdg.mdg_dgemm_split_workspace_size(m, n, k, S)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    assert mdg.mdg_dgemm_split(trans[0], trans[1], m, n, k, -0.75, dA, p["lda"], dB, p["ldb"], 0.5,
+                               dC, p["ldc"], S, ws, ws_bytes) == 0
+    torch.cuda.synchronize()
+    got = logical(dC.cpu().numpy(), m, n, p["ldc"])
+    R = sample_indices(m, 12, synth.seed_for(37, S, 5))
+    Sx = sample_indices(n, 12, synth.seed_for(37, S, 6))
+    ref_r, d_r, ref_c, d_c = sampled_reference(p, -0.75, 0.5, R, Sx)
+    er, ec = rel_err(got[R, :], ref_r, d_r), rel_err(got[:, Sx], ref_c, d_c)
+    print(f"[split] S={S} row err {er:.2e} col err {ec:.2e}", flush=True)
     assert er <= TOL and ec <= TOL

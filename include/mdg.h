@@ -62,6 +62,8 @@ extern "C" {
 #define MDG_ERR_SIZE (-4)    /* m, n too large for one launch's grid, or a leading dimension so
                                 large that the part of one k-panel inside the matrix spans 4 GiB
                                 or more (the kernels address it by 32-bit byte offsets) */
+#define MDG_ERR_SCRATCH (-5) /* the problem needs more scratch than the no-allocation entry point
+                                holds (mdg_dgemm_split_noalloc_max_bytes) */
 
 #define MDG_VARIANT_AUTO (-1)
 
@@ -168,6 +170,28 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k,
  */
 int mdg_split_slices(int operand, char trans, int64_t rows, int64_t k, const double *X, int64_t ld,
                      int nslices, int8_t *slices, int32_t *exponents, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mdg_dgemm_split without a workspace argument. The
+ * slices and exponents go to a static device array of the library, mdg_dgemm_split_noalloc_max_bytes()
+ * bytes (64 MiB) per GPU, allocated with the library's code on each device and held until the
+ * process ends; the call itself allocates and frees nothing. Arguments 1-14, the stream, the
+ * status codes and the result (bit for bit) are those of mdg_dgemm_split with a workspace of
+ * mdg_dgemm_split_workspace_size(m, n, k, nslices) bytes; a problem whose workspace size exceeds
+ * the array returns MDG_ERR_SCRATCH before any HIP call (for example m = n = k = 2048 fits with
+ * up to 7 slices). Every call on one GPU shares that GPU's array: calls whose work overlaps on the
+ * device (different streams, or host threads without ordering) race and give undefined results;
+ * calls in order on one stream are safe. The exponent arrays are cleared by a kernel on `stream`
+ * at the start of every call.
+ */
+int64_t mdg_dgemm_split_noalloc_max_bytes(void);
+
+int mdg_dgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                            double alpha, const double *A, int64_t lda,
+                            const double *B, int64_t ldb,
+                            double beta, double *C, int64_t ldc,
+                            int nslices, void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Grouped launch: many independent dgemm operations (each exactly as mdg_dgemm) in one

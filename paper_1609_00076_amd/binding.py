@@ -24,6 +24,7 @@ MDG_ERR_HIP = -1
 MDG_ERR_VARIANT = -2
 MDG_ERR_DEVICE = -3
 MDG_ERR_SIZE = -4
+MDG_ERR_SCRATCH = -5
 
 
 class mdg_gemm_desc(ctypes.Structure):
@@ -96,6 +97,10 @@ def load():
     lib.mdg_dgemm_split_workspace_size.restype = i64
     lib.mdg_dgemm_split.argtypes = gemm_args[:-1] + [ci, vp, i64, vp]
     lib.mdg_dgemm_split.restype = ci
+    lib.mdg_dgemm_split_noalloc.argtypes = gemm_args[:-1] + [ci, vp]
+    lib.mdg_dgemm_split_noalloc.restype = ci
+    lib.mdg_dgemm_split_noalloc_max_bytes.argtypes = []
+    lib.mdg_dgemm_split_noalloc_max_bytes.restype = i64
     lib.mdg_split_slices.argtypes = [ci, ch, i64, i64, vp, i64, ci, vp, vp, vp]
     lib.mdg_split_slices.restype = ci
     dptr = ctypes.POINTER(mdg_gemm_desc)
@@ -312,6 +317,17 @@ def mdg_dgemm_split(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc
     args = _marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
     ws = _raw_ptr(workspace, max(0, int(workspace_bytes)), "workspace")
     return load().mdg_dgemm_split(*args[:-1], int(nslices), ws, int(workspace_bytes), args[-1])
+
+
+def mdg_dgemm_split_noalloc_max_bytes() -> int:
+    return load().mdg_dgemm_split_noalloc_max_bytes()
+
+
+def mdg_dgemm_split_noalloc(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                            nslices, stream=None) -> int:
+    """mdg_dgemm_split on the library's static scratch array (no workspace, no allocation)."""
+    args = _marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
+    return load().mdg_dgemm_split_noalloc(*args[:-1], int(nslices), args[-1])
 
 
 def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents, stream=None) -> int:

@@ -1263,6 +1263,7 @@ const char* mdg_status_string(int status) {
     case MDG_ERR_VARIANT: return "unknown kernel variant";
     case MDG_ERR_DEVICE: return "current device is not gfx950";
     case MDG_ERR_SIZE: return "problem too large for one launch (grid size or leading dimension)";
+    case MDG_ERR_SCRATCH: return "problem needs more scratch than the no-allocation entry point holds";
     default: return "unknown status";
   }
 }

@@ -14,10 +14,12 @@
 //      apply alpha and beta in binary64.
 // A row of op(A) or column of op(B) holding NaN or Inf is flagged by the exponent pass, and the
 // epilogue writes NaN to its row or column of C (the product there is not finite).
-// Slices live in the caller's workspace as 32-deep k-panels of 1 KiB chunks of 32 rows (slice_offset), padded
+// Slices live in a workspace (the caller's, or the library's static scratch array for the
+// no-allocation entry point) as 32-deep k-panels of 1 KiB chunks of 32 rows (slice_offset), padded
 // with zeros to multiples of 128 rows and 64 k-values.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include <cstdint>
@@ -805,6 +807,41 @@ int split_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double 
                 dim3(kThreads), s, argv);  // both GEMM kernels run kThreads threads
 }
 
+// ------------------------------------------------------------------------------------------------
+// Static scratch for mdg_dgemm_split_noalloc: a file-scope device array, one copy per GPU, held
+// until the process ends. Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in for the symbol): the device address is looked up once per device with
+// hipGetSymbolAddress while that device is current, and kept.
+// ------------------------------------------------------------------------------------------------
+constexpr int64_t kScratchBytes = (int64_t)64 << 20;
+static __device__ __attribute__((aligned(256))) int8_t scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+int8_t* g_scratch_ptr[kMaxScratchDevices];
+
+int scratch_address(int8_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    mdg_record_hip_error((int)e);
+    return MDG_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices) return MDG_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      mdg_record_hip_error((int)e);
+      return MDG_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = static_cast<int8_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MDG_SUCCESS;
+}
+
 }  // namespace mdg_split_impl
 
 using namespace mdg_split_impl;
@@ -861,6 +898,31 @@ int mdg_dgemm_split(char transa, char transb, int64_t m, int64_t n, int64_t k, d
   if (st) return st;
   return split_run(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices,
                    static_cast<int8_t*>(workspace), L, static_cast<hipStream_t>(stream));
+}
+
+int64_t mdg_dgemm_split_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int mdg_dgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                            double alpha, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double beta, double* C, int64_t ldc, int nslices,
+                            void* stream) {
+  int st = split_check(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices);
+  if (st) return st;
+  const bool no_product = (alpha == 0.0 || k == 0);
+  if (m == 0 || n == 0 || (no_product && beta == 1.0)) return MDG_SUCCESS;
+  if (no_product)  // no slices and no scratch: the native entry point allocates nothing either
+    return mdg_dgemm(transa, transb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+  const Layout L = layout(m, n, k, nslices);
+  if (L.total > kScratchBytes) return MDG_ERR_SCRATCH;
+  st = split_size_check(m, n, nslices, L);
+  if (st) return st;
+  st = mdg_device_check();
+  if (st) return st;
+  int8_t* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st) return st;
+  return split_run(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices, ws, L,
+                   static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

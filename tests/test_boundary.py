@@ -217,6 +217,45 @@ def test_tri_plans_are_checked_before_any_launch(name):
     assert _tri(name, m=300, n=200, lda=300, ldb=40_000_000) == -4
 
 
+@pytest.mark.parametrize("kw,code", [
+    (dict(ta="X"), 1), (dict(tb="q"), 2), (dict(m=-1), 3), (dict(n=-2), 4), (dict(k=-3), 5),
+    (dict(A=None), 7), (dict(lda=3), 8), (dict(B=None), 9), (dict(ldb=3), 10),
+    (dict(C=None), 12), (dict(ldc=3), 13), (dict(S=0), 14), (dict(S=11), 14),
+])
+def test_split_noalloc_argument_codes(kw, code):
+    """The no-allocation split entry point checks arguments as mdg_dgemm_split does (fake
+    addresses, never dereferenced: each call fails a check before any HIP call)."""
+    a = dict(ta="N", tb="N", m=4, n=4, k=4, alpha=1.0, A=0x1000, lda=4, B=0x1000, ldb=4, beta=0.0,
+             C=0x1000, ldc=4, S=7)
+    a.update(kw)
+    st = mdg.mdg_dgemm_split_noalloc(a["ta"], a["tb"], a["m"], a["n"], a["k"], a["alpha"], a["A"],
+                                     a["lda"], a["B"], a["ldb"], a["beta"], a["C"], a["ldc"],
+                                     a["S"])
+    assert st == code
+
+
+def test_split_noalloc_scratch_limit_is_host_side():
+    """Problems whose workspace exceeds the static scratch array are refused with MDG_ERR_SCRATCH
+    before any HIP call; quick returns need no scratch."""
+    cap = mdg.mdg_dgemm_split_noalloc_max_bytes()
+    assert cap == 64 << 20
+    fake = 1 << 40
+    assert mdg.mdg_dgemm_split_workspace_size(2048, 2048, 2048, 7) <= cap
+    assert mdg.mdg_dgemm_split_workspace_size(2048, 2048, 2048, 8) > cap
+    st = mdg.mdg_dgemm_split_noalloc("N", "N", 2048, 2048, 2048, 1.0, fake, 2048, fake, 2048, 0.0,
+                                     fake, 2048, 8)
+    assert st == mdg.MDG_ERR_SCRATCH
+    assert "scratch" in mdg.mdg_status_string(st)
+    # a problem that fits passes the limit and stops at the device check here (no GPU)
+    st = mdg.mdg_dgemm_split_noalloc("N", "N", 2048, 2048, 2048, 1.0, fake, 2048, fake, 2048, 0.0,
+                                     fake, 2048, 7)
+    assert st in (mdg.MDG_ERR_HIP, mdg.MDG_ERR_DEVICE)
+    assert mdg.mdg_dgemm_split_noalloc("N", "N", 0, 5, 5, 1.0, None, 1, None, 5, 0.0, None, 1,
+                                       7) == 0
+    assert mdg.mdg_dgemm_split_noalloc("N", "N", 5, 5, 5, 0.0, None, 5, None, 5, 1.0, None, 5,
+                                       7) == 0
+
+
 def test_split_entry_points_check_the_device_after_the_arguments():
     """Argument and size checks come first; then, before any launch, the device check (on this
     CPU-only host it fails with a runtime code rather than launching)."""

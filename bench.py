@@ -7,6 +7,11 @@ m = n = 8192, k = 64 (28 GEMMs), ld = stored rows rounded up to a multiple of 8,
 alpha = beta = 1, Uniform[-1,1] entries drawn by the seeded generator and
 resident in HBM before timing starts. value = total 2mnk flops / timed seconds.
 
+The same line also carries, under "workloads", the other four workloads, each timed after the
+sweep with its own CPU-oracle baseline: the plain NN 256^3 call (lda = ldb = ldc = 260), the
+split-precision path at NN 8192^3 for exponent spreads 0, 8 and 32 against the native kernel, the
+2048-GEMM grouped batch as a graph replay, and the 60-second served stream.
+
 Prints ONE JSON line (rank 0). Only one GPU is supported: --gpus above 1 exits.
 """
 from __future__ import annotations
@@ -154,95 +159,222 @@ def cpu_baseline(probs, budget_s: float, threads: int = 0):
     return total_flops / total_t / 1e12, threads, desc
 
 
+
+def host_cores():
+    """(threads the oracle uses, affinity mask of this process as ranges, os.cpu_count())."""
+    try:
+        cpus = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = list(range(os.cpu_count() or 1))
+    ranges, start = [], None
+    for i, c in enumerate(cpus):
+        if start is None:
+            start = c
+        if i + 1 == len(cpus) or cpus[i + 1] != c + 1:
+            ranges.append(f"{start}" if start == c else f"{start}-{c}")
+            start = None
+    return ",".join(ranges), os.cpu_count()
+
+
+def sample_lines(size: int, count: int, seed: int):
+    """Sorted unique indices of rows (or columns): the edges, tile boundaries and seeded ones."""
+    import numpy as np
+
+    import synth
+    fixed = [0, 1, 15, 16, 63, 64, 127, 128, 129, 255, 256, size // 2, size - 2, size - 1]
+    rnd = synth.rng(seed).integers(0, size, count).tolist() if size > 0 else []
+    return np.array(sorted({i for i in fixed + rnd if 0 <= i < size}), dtype=np.int64)
+
+
+def oracle_lines(hA, hB, hC, m, n, k, lda, ldb, ldc, alpha, beta, R, S, fn="dgemm", at=None):
+    """The oracle's full rows R and full columns S of C for an NN problem on host storage, and the
+    error denominators D of the same entries. The needed rows of A and columns of B are copied out
+    (data movement only; `at` may hold A transposed to k-contiguous rows already), so the oracle
+    evaluates exactly the products and order of the whole problem, each entry a dot product over
+    contiguous memory. Returns (rows |R| x n, D rows, cols m x |S|, D cols, multiply-adds)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    Av = synth.view2d(hA, m, k, lda)
+    Bv = synth.view2d(hB, k, n, ldb)
+    C0 = synth.view2d(hC, m, n, ldc)
+    f = getattr(oracle, fn)
+    ar = np.ascontiguousarray(Av[R, :]).reshape(-1)          # op(A)[R, :]^T stored k x |R|
+    c0r = np.asfortranarray(C0[R, :]).reshape(-1, order="F")
+    cr = c0r.copy()
+    assert f("T", "N", len(R), n, k, alpha, ar, k, hB, ldb, beta, cr, len(R)) == 0
+    dr = np.zeros(len(R) * n)
+    assert oracle.absden("T", "N", len(R), n, k, alpha, ar, k, hB, ldb, beta, c0r, len(R), dr,
+                         len(R)) == 0
+    bs = np.asfortranarray(Bv[:, S]).reshape(-1, order="F")  # op(B)[:, S] stored k x |S|
+    c0s = np.asfortranarray(C0[:, S]).reshape(-1, order="F")
+    if at is None:
+        at = np.ascontiguousarray(Av).reshape(-1)            # op(A)^T stored k x m
+    cs = c0s.copy()
+    assert f("T", "N", m, len(S), k, alpha, at, k, bs, k, beta, cs, m) == 0
+    ds = np.zeros(m * len(S))
+    assert oracle.absden("T", "N", m, len(S), k, alpha, at, k, bs, k, beta, c0s, m, ds, m) == 0
+    macs = float(len(R) * n + m * len(S)) * k
+    return (cr.reshape(n, len(R)).T, dr.reshape(n, len(R)).T, cs.reshape(len(S), m).T,
+            ds.reshape(len(S), m).T, macs)
+
+
+def max_rel_err(got, ref, D):
+    """max |got - ref| / D (entries with D = 0 must be equal, else inf)."""
+    import numpy as np
+    diff = np.abs(got - ref)
+    zero = D == 0
+    if np.any(zero & (diff != 0)) or np.any(np.isnan(diff)):
+        return float("inf")
+    return float(np.max(np.where(zero, 0.0, diff / np.where(zero, 1.0, D)))) if diff.size else 0.0
+
 SPLIT_CASES = [(0, 7), (8, 8), (32, 10)]  # (phi, nslices) that reach err <= 1e-13
 INT8_PEAK_TOPS = 5000.0
 
 
-def split_workload(args, torch, mdg):
-    """Split-precision dgemm (INT8 MFMA slices) against the native FP64 kernel, NN 8192^3."""
+def events_ms(torch, fn, reps, warmup):
+    """Average milliseconds per call of fn() over `reps` calls on the current stream (HIP events
+    around the whole run), after `warmup` untimed calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def split_result(args, torch, mdg):
+    """Workload 3: split-precision dgemm (INT8 MFMA slices) against the native FP64 kernel, NN
+    8192^3, phi in {0, 8, 32}. Times the whole split call, the two slicing steps alone (so the
+    slice-product GEMM kernel's time is the difference) and the native call; in the CPU-baseline
+    leg the oracle computes sampled full rows and columns, which are timed and also give the split
+    and native results' errors (and a doubled-precision sample gives the true error)."""
     import numpy as np
 
     import synth
     m = n = k = args.split_size
-    results = []
+    cases, cpu_parts = [], []
+    cpu_flops = cpu_s = 0.0
     for phi, S in SPLIT_CASES:
         dist = "scaled" if phi else "uniform"
         p = synth.problem(3, phi, "N", "N", m, n, k, ld_rule=synth.ld_round8, dist=dist, phi=phi)
+        lda, ldb, ldc = p["lda"], p["ldb"], p["ldc"]
         dA, dB, dC0 = (torch.from_numpy(p[x]).cuda() for x in "ABC")
         ws_bytes = mdg.mdg_dgemm_split_workspace_size(m, n, k, S)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         dC = dC0.clone()
+        rp, kp = (m + 127) // 128 * 128, (k + 63) // 64 * 64
+        sl = torch.empty(S * rp * kp, dtype=torch.int8, device="cuda")
+        ex = torch.empty(max(m, n), dtype=torch.int32, device="cuda")
+
+        def check(st):
+            if st:
+                raise RuntimeError(mdg.mdg_status_string(st))
 
         def split_call():
-            st = mdg.mdg_dgemm_split("N", "N", m, n, k, 1.0, dA, p["lda"], dB, p["ldb"], 1.0, dC,
-                                     p["ldc"], S, ws, ws_bytes)
-            if st:
-                raise RuntimeError(mdg.mdg_status_string(st))
+            check(mdg.mdg_dgemm_split("N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 1.0, dC, ldc, S, ws,
+                                      ws_bytes))
 
         def native_call():
-            st = mdg.mdg_dgemm("N", "N", m, n, k, 1.0, dA, p["lda"], dB, p["ldb"], 1.0, dC,
-                               p["ldc"])
-            if st:
-                raise RuntimeError(mdg.mdg_status_string(st))
+            check(mdg.mdg_dgemm("N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 1.0, dC, ldc))
 
-        times = {}
-        for name, fn in (("split", split_call), ("native", native_call)):
-            for _ in range(args.warmup):
-                fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(args.steps):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            times[name] = e0.elapsed_time(e1) / args.steps
-        # Accuracy over the whole of C, on the GPU: one split call and one native call from the
-        # original C, and D = |A||B| + |C0| from a native call on absolute values. The native FP64
-        # result is within rounding (about 1e-16 D) of the exact one, so this bounds the split
-        # error against the exact product to that margin. (The test suite checks the same inputs
-        # against the CPU oracle.)
+        def slicing_only():
+            check(mdg.mdg_split_slices(0, "N", m, k, dA, lda, S, sl, ex))
+            check(mdg.mdg_split_slices(1, "N", n, k, dB, ldb, S, sl, ex))
+
+        split_ms = events_ms(torch, split_call, args.steps, args.warmup)
+        native_ms = events_ms(torch, native_call, args.steps, args.warmup)
+        slice_ms = events_ms(torch, slicing_only, args.steps, args.warmup)
+        gemm_ms = split_ms - slice_ms
+        # one result of each path from the original C, for the error figures
         dC.copy_(dC0)
         split_call()
-        c_split = dC.clone()
+        c_split = dC.view(n, ldc)[:, :m].T.cpu().numpy()
         dC.copy_(dC0)
         native_call()
-        dD = dC0.abs()
-        st = mdg.mdg_dgemm("N", "N", m, n, k, 1.0, dA.abs(), p["lda"], dB.abs(), p["ldb"], 1.0, dD,
-                           p["ldc"])
-        if st:
-            raise RuntimeError(mdg.mdg_status_string(st))
-        ld = p["ldc"]
-        diff = (c_split.view(n, ld)[:, :m] - dC.view(n, ld)[:, :m]).abs()
-        den = dD.view(n, ld)[:, :m]
-        ratio = torch.where(den > 0, diff / den, torch.where(diff > 0, float("inf"), 0.0))
-        err = float(ratio.max())
-        del dA, dB, dC, dC0, dD, ws, c_split, diff, den, ratio
+        c_native = dC.view(n, ldc)[:, :m].T.cpu().numpy()
+        del dA, dB, dC, dC0, ws, sl, ex
+        torch.cuda.empty_cache()
         fl = 2.0 * m * n * k
         products = S * (S + 1) // 2
-        results.append({
+        case = {
             "phi": phi, "nslices": S, "slice_products": products,
-            "split_ms": round(times["split"], 3), "native_ms": round(times["native"], 3),
-            "split_tflops_equiv": round(fl / (times["split"] * 1e-3) / 1e12, 2),
-            "native_tflops": round(fl / (times["native"] * 1e-3) / 1e12, 2),
-            "int8_tops_in_call": round(products * fl / (times["split"] * 1e-3) / 1e12, 1),
-            "speedup_vs_native": round(times["native"] / times["split"], 3),
-            "max_err_vs_native_fp64": float(f"{err:.3g}"),
-        })
-        log(f"[bench] split phi={phi} S={S}: {results[-1]}")
-    best = max(results, key=lambda r: r["split_tflops_equiv"])
+            "split_ms": round(split_ms, 3), "native_ms": round(native_ms, 3),
+            "slicing_ms": round(slice_ms, 3), "gemm_kernel_ms": round(gemm_ms, 3),
+            "split_tflops_equiv": round(fl / (split_ms * 1e-3) / 1e12, 2),
+            "native_tflops": round(fl / (native_ms * 1e-3) / 1e12, 2),
+            "speedup_vs_native": round(native_ms / split_ms, 3),
+            "int8_tops_gemm_kernel": round(products * fl / (gemm_ms * 1e-3) / 1e12, 1),
+            "int8_frac_gemm_kernel": round(products * fl / (gemm_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS,
+                                           4),
+            "max_err_vs_oracle": None, "native_max_err_vs_oracle": None,
+            "true_err_vs_doubled_precision": None,
+        }
+        if args.cpu_budget > 0:
+            # CPU-baseline leg: the oracle on sampled full rows and columns (timed), whose values
+            # also state both GPU results' error.
+            R = sample_lines(m, 4, synth.seed_for(3, phi, 5))
+            Sx = sample_lines(n, 4, synth.seed_for(3, phi, 6))
+            at = np.ascontiguousarray(synth.view2d(p["A"], m, k, lda)).reshape(-1)
+            t0 = time.perf_counter()
+            ref_r, d_r, ref_c, d_c, macs = oracle_lines(p["A"], p["B"], p["C"], m, n, k, lda, ldb,
+                                                        ldc, 1.0, 1.0, R, Sx, at=at)
+            dt = time.perf_counter() - t0
+            cpu_flops += 2.0 * macs  # the denominators' pass is not counted
+            cpu_s += dt
+            cpu_parts.append(f"phi={phi}: {len(R)} rows + {len(Sx)} columns ({dt:.1f} s)")
+            case["max_err_vs_oracle"] = float(f"{max(max_rel_err(c_split[R, :], ref_r, d_r), max_rel_err(c_split[:, Sx], ref_c, d_c)):.3g}")
+            case["native_max_err_vs_oracle"] = float(f"{max(max_rel_err(c_native[R, :], ref_r, d_r), max_rel_err(c_native[:, Sx], ref_c, d_c)):.3g}")
+            R2, S2 = R[:3], Sx[-3:]
+            dd_r, _, dd_c, _, _ = oracle_lines(p["A"], p["B"], p["C"], m, n, k, lda, ldb, ldc, 1.0,
+                                               1.0, R2, S2, fn="dgemm_dd", at=at)
+            del at
+            d_r2, d_c2 = d_r[:3], d_c[:, -3:]
+            case["true_err_vs_doubled_precision"] = float(f"{max(max_rel_err(c_split[R2, :], dd_r, d_r2), max_rel_err(c_split[:, S2], dd_c, d_c2)):.3g}")
+        cases.append(case)
+        log(f"[bench] split phi={phi} S={S}: {case}")
+        del c_split, c_native, p
+    cpu = None
+    if cpu_s > 0:
+        mask, ncpu = host_cores()
+        import oracle
+        cpu = {"value": cpu_flops / cpu_s / 1e12, "unit": "TFLOP/s", "cores": oracle.get_threads(),
+               "affinity": mask, "cpu_count": ncpu, "kind": "oracle",
+               "sample": "oracle on sampled full rows and columns of C of each 8192^3 case: " +
+                         "; ".join(cpu_parts)}
+    best = max(cases, key=lambda r: r["split_tflops_equiv"])
+    return {
+        "workload": f"split-precision dgemm NN {m}x{n}x{k}, ld rounded to 8, alpha=beta=1, "
+                    "entries u*2^e, u ~ U[-1,1), e ~ U{-phi..phi}",
+        "unit": "TFLOP/s (FP64-equivalent)",
+        "cases": cases,
+        "roofline": {"bound": "mfma", "kernel": f"slice-product GEMM, {best['nslices']} slices "
+                                                f"(phi={best['phi']})",
+                     "achieved": best["int8_tops_gemm_kernel"], "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s (int8)", "frac": best["int8_frac_gemm_kernel"],
+                     "note": "kernel time = whole split call minus the two slicing steps timed "
+                             "alone"},
+        "cpu_baseline": cpu,
+    }
+
+
+def split_workload(args, torch, mdg):
+    r = split_result(args, torch, mdg)
+    best = max(r["cases"], key=lambda c: c["split_tflops_equiv"])
     out = {
         "metric": METRIC + " (split-precision leg)",
         "value": best["split_tflops_equiv"], "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8 slices, f64 recombination",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8 slices, f64 recombination",
         "data": "synthetic: seeded u*2^e, u ~ U[-1,1), e ~ U{-phi..phi}",
-        "config": {"workload": f"split-precision dgemm NN {m}x{n}x{k}, ld rounded to 8, alpha=beta=1",
-                   "cases": results},
-        "roofline": {"bound": "mfma", "peak": INT8_PEAK_TOPS, "unit": "TOP/s (int8)",
-                     "achieved": best["int8_tops_in_call"],
-                     "frac": round(best["int8_tops_in_call"] / INT8_PEAK_TOPS, 4),
-                     "note": "whole call (slicing + fused GEMM) time; the kernel alone is in profiles/"},
+        "config": {"workload": r["workload"], "cases": r["cases"]},
+        "roofline": r["roofline"], "cpu_baseline": r["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
 
@@ -254,8 +386,10 @@ def grouped_problems(count=2048, lo=16, hi=512, seed_variant=0):
     return synth.grouped_batch(count, lo, hi, seed_variant)
 
 
-def grouped_workload(args, torch, mdg):
-    """2048 uneven GEMMs: one grouped launch replayed from a graph, against per-GEMM launches."""
+def grouped_result(args, torch, mdg):
+    """Workload 4: 2048 uneven GEMMs as one grouped launch replayed from a graph, against the
+    eager grouped launch and against one mdg_dgemm launch per GEMM."""
+    import oracle
     from paper_1609_00076_amd import tuner
     from paper_1609_00076_amd.grouped import GroupedPlan
     probs = grouped_problems()
@@ -277,20 +411,8 @@ def grouped_workload(args, torch, mdg):
         policy = tuner.best_policy(tuner.GROUPED_SIGNATURE, db_path=db)
     log(f"[bench] policy {policy}")
 
-    def timed(fn, reps):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-
-    plan = GroupedPlan(gemms, tuner.classes_for(gemms, policy["threshold"]), policy["schedule"])
-    eager_grouped = timed(lambda: plan.launch(policy["grid"]), args.steps)
+    plan = GroupedPlan(gemms, tuner.classes_for(gemms, policy), policy["schedule"])
+    eager_grouped = events_ms(torch, lambda: plan.launch(policy["grid"]), args.steps, args.warmup)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -299,7 +421,7 @@ def grouped_workload(args, torch, mdg):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         plan.launch(policy["grid"])
-    graph_ms = timed(graph.replay, args.steps)
+    graph_ms = events_ms(torch, graph.replay, args.steps, args.warmup)
 
     def per_gemm():
         for g in gemms:
@@ -307,20 +429,36 @@ def grouped_workload(args, torch, mdg):
                                g["A"], g["lda"], g["B"], g["ldb"], g["beta"], g["C"], g["ldc"])
             if st:
                 raise RuntimeError(mdg.mdg_status_string(st))
-    separate_ms = timed(per_gemm, max(1, args.steps // 4))
+    separate_ms = events_ms(torch, per_gemm, max(1, args.steps // 4), 1)
     value = total_flops / (graph_ms * 1e-3) / 1e12
-    out = {
-        "metric": METRIC + " (grouped-launch leg)",
-        "value": round(value, 3), "unit": "TFLOP/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic: seeded U[-1,1) FP64, shapes log-uniform in [16,512]",
-        "config": {"workload": "2048 independent dgemm, m,n,k log-uniform integers in [16,512], "
-                               "transposes iid, alpha,beta ~ U[-1,1), tight ld; one grouped "
-                               "persistent launch replayed from a graph",
-                   "policy": policy, "tiles": plan.num_tiles,
-                   "total_flops": total_flops, "algorithmic_bytes": total_bytes},
+    cpu = None
+    if args.cpu_budget > 0:
+        # the oracle on the batch's GEMMs in order until a share of the budget is spent
+        import numpy as np
+        t_spent, fl, count = 0.0, 0.0, 0
+        for p in probs:
+            c = p["C"].copy()
+            t0 = time.perf_counter()
+            assert oracle.dgemm(p["transa"], p["transb"], p["m"], p["n"], p["k"], p["alpha"],
+                                p["A"], p["lda"], p["B"], p["ldb"], p["beta"], c, p["ldc"]) == 0
+            t_spent += time.perf_counter() - t0
+            fl += 2.0 * p["m"] * p["n"] * p["k"]
+            count += 1
+            if t_spent > args.cpu_budget / 4:
+                break
+        del np
+        mask, ncpu = host_cores()
+        cpu = {"value": fl / t_spent / 1e12, "unit": "TFLOP/s", "cores": oracle.get_threads(),
+               "affinity": mask, "cpu_count": ncpu, "kind": "oracle",
+               "sample": f"oracle on the first {count} GEMMs of the batch ({t_spent:.1f} s)"}
+    return {
+        "workload": "2048 independent dgemm, m,n,k log-uniform integers in [16,512], transposes "
+                    "iid, alpha,beta ~ U[-1,1), tight ld; one grouped persistent launch replayed "
+                    "from a graph",
+        "policy": policy, "tiles": plan.num_tiles,
+        "total_flops": total_flops, "algorithmic_bytes": total_bytes,
         "graph_replay_ms": round(graph_ms, 4),
+        "tflops": round(value, 3),
         "eager_grouped_ms": round(eager_grouped, 4),
         "separate_launches_ms": round(separate_ms, 4),
         "speedup_vs_separate": round(separate_ms / graph_ms, 2),
@@ -328,35 +466,170 @@ def grouped_workload(args, torch, mdg):
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(total_bytes / (graph_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                      "mfma_frac": round(value / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+
+
+def grouped_workload(args, torch, mdg):
+    r = grouped_result(args, torch, mdg)
+    out = {
+        "metric": METRIC + " (grouped-launch leg)",
+        "value": r["tflops"], "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["graph_replay_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic: seeded U[-1,1) FP64, shapes log-uniform in [16,512]",
+        "config": {k: r[k] for k in ("workload", "policy", "tiles", "total_flops",
+                                     "algorithmic_bytes")},
+        **{k: r[k] for k in ("graph_replay_ms", "eager_grouped_ms", "separate_launches_ms",
+                             "speedup_vs_separate", "roofline", "cpu_baseline")},
     }
     print(json.dumps(out), flush=True)
 
 
-def served_workload(args, torch, mdg):
-    """Poisson stream of dgemm requests through the continuous-batching server."""
+def served_result(args, torch, mdg):
+    """Workload 5: a Poisson stream of dgemm requests through the continuous-batching server."""
+    import numpy as np
+
+    import oracle
+    import synth
     from paper_1609_00076_amd import serve
     reqs = serve.make_stream(args.rate, args.duration, seed=synth_seed(5), lo=32, hi=4096,
                              split_fraction=0.2, phi=8)
     log(f"[bench] serving {len(reqs)} requests over {args.duration} s")
     warm = serve.make_stream(200, 0.5, seed=synth_seed(5) + 1, lo=32, hi=512)
     srv = serve.Server(budget_bytes=args.budget_gb << 30)
-    srv.run(warm)  # compile-free warm-up of allocator and streams
+    srv.run(warm)  # warm-up of allocator and streams
     stats = srv.run(reqs)
     s = stats.summary()
     log(f"[bench] served: {s}")
+    cpu = None
+    if args.cpu_budget > 0:
+        # the oracle on the stream's first requests (same shapes, seeded host data), in order,
+        # until a share of the budget is spent
+        t_spent, fl, count = 0.0, 0.0, 0
+        for r in reqs:
+            ra, ca = r.stored("A")
+            rb, cb = r.stored("B")
+            g = synth.rng(r.seed % (1 << 32))
+            A, B, C = (g.uniform(-1, 1, max(1, x * y)) for x, y in ((ra, ca), (rb, cb), (r.m, r.n)))
+            t0 = time.perf_counter()
+            assert oracle.dgemm(r.transa, r.transb, r.m, r.n, r.k, r.alpha, A, max(1, ra), B,
+                                max(1, rb), r.beta, C, max(1, r.m)) == 0
+            t_spent += time.perf_counter() - t0
+            fl += r.flops
+            count += 1
+            if t_spent > args.cpu_budget / 4:
+                break
+        del np
+        mask, ncpu = host_cores()
+        cpu = {"value": fl / t_spent / 1e12, "unit": "TFLOP/s", "cores": oracle.get_threads(),
+               "affinity": mask, "cpu_count": ncpu, "kind": "oracle",
+               "sample": f"oracle on the first {count} requests of the stream ({t_spent:.1f} s)"}
+    return {
+        "workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, m,n,k log-uniform in "
+                    "[32,4096], transposes iid, 80% native, 20% split (phi=8, "
+                    f"{serve.SPLIT_SLICES[8]} slices), HBM budget {args.budget_gb} GiB",
+        "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "aggregate_tflops": s["aggregate_tflops"],
+        "served": s, "cpu_baseline": cpu,
+    }
+
+
+def served_workload(args, torch, mdg):
+    r = served_result(args, torch, mdg)
+    s = r["served"]
     out = {
         "metric": METRIC + " (served-stream leg)",
         "value": s["aggregate_tflops"], "unit": "TFLOP/s",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * s["wall_s"], 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic: operands filled on the device from per-request seeds",
-        "config": {"workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, m,n,k "
-                               "log-uniform in [32,4096], transposes iid, 80% native, 20% split "
-                               f"(phi=8, {serve.SPLIT_SLICES[8]} slices), HBM budget "
-                               f"{args.budget_gb} GB"},
-        "served": s,
+        "config": {"workload": r["workload"]},
+        "served": s, "cpu_baseline": r["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
+
+
+PLAIN = dict(m=256, n=256, k=256, ld=260, alpha=1.5, beta=0.5)
+
+
+def plain_result(args, torch, mdg):
+    """Workload 1: NN 256^3 with lda = ldb = ldc = 260, alpha = 1.5, beta = 0.5, uniform entries
+    (and the integer-valued variant for a bit-exact check in the CPU-baseline leg)."""
+    import numpy as np
+
+    import synth
+    m, n, k, ld, alpha, beta = (PLAIN[x] for x in ("m", "n", "k", "ld", "alpha", "beta"))
+    out = {"workload": f"dgemm NN {m}x{n}x{k}, lda=ldb=ldc={ld}, alpha={alpha}, beta={beta}, "
+                       "U[-1,1) entries"}
+    results = {}
+    for dist in ("uniform", "int"):
+        p = synth.problem(1, 0, "N", "N", m, n, k, ld_rule=lambda r: ld, dist=dist)
+        dA, dB, dC0 = (torch.from_numpy(p[x]).cuda() for x in "ABC")
+        dC = dC0.clone()
+
+        def call():
+            st = mdg.mdg_dgemm("N", "N", m, n, k, alpha, dA, ld, dB, ld, beta, dC, ld)
+            if st:
+                raise RuntimeError(mdg.mdg_status_string(st))
+        if dist == "uniform":
+            reps = max(200, 20 * args.steps)
+            # per-call events: the median call, and the back-to-back average
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for _ in range(args.warmup + 5):
+                call()
+            torch.cuda.synchronize()
+            for e0, e1 in ev:
+                e0.record()
+                call()
+                e1.record()
+            torch.cuda.synchronize()
+            t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+            med_us = 1e3 * t[len(t) // 2]
+            avg_us = 1e3 * events_ms(torch, call, reps, 0)
+            fl = 2.0 * m * n * k
+            by = 8.0 * (2 * m * k + 2 * m * n)
+            out.update({
+                "median_us": round(med_us, 2), "back_to_back_avg_us": round(avg_us, 2),
+                "tflops": round(fl / (med_us * 1e-6) / 1e12, 3),
+                "frac_of_fp64_mfma_peak": round(fl / (med_us * 1e-6) / 1e12 / PEAK_FP64_MFMA_TFLOPS, 5),
+                "gbs": round(by / (med_us * 1e-6) / 1e9, 1),
+                "frac_of_hbm_peak": round(by / (med_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 5),
+                "variant": mdg.mdg_variant_name(mdg.mdg_select_variant("N", "N", m, n, k, alpha,
+                                                                      beta)),
+            })
+        dC.copy_(dC0)
+        call()
+        results[dist] = (p, synth.view2d(dC.cpu().numpy(), m, n, ld).copy())
+    cpu = None
+    if args.cpu_budget > 0:
+        # CPU-baseline leg: the oracle on the same problem, repeated; its values also check the
+        # GPU results (bit-exact on integers, error relative to D on uniform entries)
+        import oracle
+        p, got = results["uniform"]
+        reps, t_spent = 0, 0.0
+        while t_spent < min(2.0, args.cpu_budget / 8):
+            ref = p["C"].copy()
+            t0 = time.perf_counter()
+            assert oracle.dgemm("N", "N", m, n, k, alpha, p["A"], ld, p["B"], ld, beta, ref, ld) == 0
+            t_spent += time.perf_counter() - t0
+            reps += 1
+        D = np.zeros(m * n)
+        assert oracle.absden("N", "N", m, n, k, alpha, p["A"], ld, p["B"], ld, beta, p["C"], ld, D,
+                             m) == 0
+        out["max_err_vs_oracle"] = float(f"{max_rel_err(got, synth.view2d(ref, m, n, ld), D.reshape(n, m).T):.3g}")
+        pi, goti = results["int"]
+        refi = pi["C"].copy()
+        assert oracle.dgemm("N", "N", m, n, k, alpha, pi["A"], ld, pi["B"], ld, beta, refi, ld) == 0
+        out["integer_variant_bit_exact"] = bool(np.array_equal(goti, synth.view2d(refi, m, n, ld)))
+        mask, ncpu = host_cores()
+        cpu = {"value": reps * 2.0 * m * n * k / t_spent / 1e12, "unit": "TFLOP/s",
+               "cores": oracle.get_threads(), "affinity": mask, "cpu_count": ncpu,
+               "kind": "oracle", "sample": f"oracle on the whole problem, {reps} times "
+                                           f"({t_spent:.1f} s)"}
+    out["cpu_baseline"] = cpu
+    return out
 
 
 BLAS3_SIZE = 8192
@@ -509,11 +782,12 @@ def main():
     ap.add_argument("--trans", default="", help="comma list of NN,NT,TN,TT (default: all four)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force one kernel variant for every GEMM (default -1: the library's choice)")
-    ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "split", "grouped", "served", "blas3"],
-                    help="sweep: the native dgemm sweep (default, the headline line); split: the "
-                         "split-precision INT8 path against the native kernel; blas3: dsyrk, "
-                         "dtrmm and dtrsm built on the GEMM")
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "sweep", "plain", "split", "grouped", "served", "blas3"],
+                    help="all (default): the native dgemm sweep (the headline value) and, in the "
+                         "same line, the plain 256^3 call, the split-precision path, the grouped "
+                         "batch and the served stream; sweep: the sweep alone; split, grouped, "
+                         "served: one of those alone; blas3: dsyrk, dtrmm and dtrsm on the GEMM")
     ap.add_argument("--split-size", type=int, default=8192)
     ap.add_argument("--tune", action="store_true", help="grouped: run the autotuner first")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
@@ -550,6 +824,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
         return
 
+    if args.workload == "plain":
+        print(json.dumps(plain_result(args, torch, mdg)), flush=True)
+        return
     if args.workload == "split":
         split_workload(args, torch, mdg)
         return
@@ -634,8 +911,28 @@ def main():
         log("[bench] timing the CPU oracle baseline")
         v, cores, desc = cpu_baseline(probs, args.cpu_budget)
         v1, _, desc1 = cpu_baseline(probs, args.cpu_budget / 3, threads=1)
-        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc,
-               "value_1_thread": v1, "sample_1_thread": desc1}
+        mask, ncpu = host_cores()
+        cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "affinity": mask, "cpu_count": ncpu,
+               "kind": "oracle", "sample": desc, "value_1_thread": v1,
+               "sample_1_thread": desc1}
+    workload_desc = ("native dgemm sweep: (N|T)x(N|T) x square m=n=k in "
+                     "{1024,2048,4096,4099,8192,16384} + 8192x8192x64; ld = stored rows rounded "
+                     "up to a multiple of 8; alpha=beta=1" if not subset else
+                     "native dgemm subset: " + ", ".join(out_workload(probs)))
+    n_gemms = len(probs)
+    del probs, ev
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    workloads = None
+    if args.workload == "all" and not subset:
+        workloads = {}
+        for name, fn in (("plain_256", plain_result), ("split_8192", split_result),
+                         ("grouped_2048", grouped_result), ("served", served_result)):
+            log(f"[bench] workload {name}")
+            workloads[name] = fn(args, torch, mdg)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -652,13 +949,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic: seeded Uniform[-1,1] FP64, resident in HBM before timing",
         "config": {
-            "workload": "native dgemm sweep: (N|T)x(N|T) x square m=n=k in "
-                        "{1024,2048,4096,4099,8192,16384} + 8192x8192x64; ld = stored rows rounded "
-                        "up to a multiple of 8; alpha=beta=1" if not subset else
-                        "native dgemm subset: " + ", ".join(
-                            sorted({f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}"
-                                    for p in probs})),
-            "gemms_per_step": len(probs),
+            "workload": workload_desc,
+            "gemms_per_step": n_gemms,
             "flops_per_step": step_flops,
         },
         "roofline": {
@@ -675,6 +967,8 @@ def main():
         "cpu_baseline": cpu,
         "per_problem_tflops": breakdown,
     }
+    if workloads is not None:
+        out["workloads"] = workloads
     print(json.dumps(out), flush=True)
 
 

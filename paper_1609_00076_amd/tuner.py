@@ -24,7 +24,9 @@ DEFAULT_POLICY = {"threshold": 48, "schedule": b.MDG_SCHEDULE_LPT, "grid": 1024}
 GROUPED_SIGNATURE = "grouped|2048|mnk~logU[16,512]|trans iid|tight ld"
 
 
-def classes_for(gemms, threshold):
+def classes_for(gemms, policy):
+    """Tile class of each GEMM under `policy` (a policy dict, or a bare threshold)."""
+    threshold = policy["threshold"] if isinstance(policy, dict) else policy
     return [1 if min(g["m"], g["n"]) < threshold else 0 for g in gemms]
 
 

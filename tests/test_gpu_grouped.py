@@ -162,7 +162,7 @@ def test_full_batch_graph_replays_match_oracle():
     gemms = _to_device(probs)
     c0 = [g["C"].clone() for g in gemms]
     policy = tuner.best_policy(tuner.GROUPED_SIGNATURE)
-    classes = tuner.classes_for(gemms, policy["threshold"])
+    classes = tuner.classes_for(gemms, policy)
     for grid in (policy["grid"], 0):
         plan = GroupedPlan(gemms, classes, policy["schedule"])
         s = torch.cuda.Stream()

@@ -200,15 +200,20 @@ int mdg_dgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int6
  * 1. mdg_grouped_plan (host only, no HIP call) validates every GEMM and writes a plan: one
  *    descriptor per GEMM (device pointers and sizes copied from `descs`) and the list of output
  *    tiles in schedule order. tile_class[i] (NULL = automatic: 1 when m < 48 or n < 48, else 0)
- *    picks the tile of GEMM i: 0 = 64x64 (the tile of variant "mfma_f64_64x64x16_w32x32"),
- *    1 = 32x32 (variant "mfma_f64_32x32x16_w16x16"); results are bitwise those of mdg_dgemm_ex
- *    with that variant. schedule: MDG_SCHEDULE_NATURAL (GEMM by GEMM) or MDG_SCHEDULE_LPT
- *    (tiles by decreasing cost, i.e. tile area times k).
+ *    picks the tile of GEMM i: 0 = 64x64 workgroup tile (the tile of variant
+ *    "mfma_f64_64x64x16_w32x32"), 1 = 32x32 workgroup tile (variant "mfma_f64_32x32x16_w16x16"),
+ *    2 = 32x32 wave tile (variant "wave_f64_64x64x8_w32x32": each wave computes its own tiles
+ *    with no LDS or barrier; bitwise the result of that variant and of the "ring_" variants).
+ *    Class 2 cannot be mixed with classes 0 and 1 in one plan (code 3). schedule:
+ *    MDG_SCHEDULE_NATURAL (GEMM by GEMM) or MDG_SCHEDULE_LPT (tiles by decreasing cost, i.e. tile
+ *    area times k). In a class-2 plan every GEMM goes to one XCD (LPT: by decreasing cost to the
+ *    least loaded XCD; NATURAL: round-robin) and each XCD's waves walk its own tile sublist.
  * 2. The caller copies the plan bytes to device memory (16-byte aligned) and keeps them, and the
  *    matrices the descriptors point to, alive and unchanged while launches are pending.
- * 3. mdg_dgemm_grouped launches one persistent kernel of `grid` workgroups (0 = 4 per CU) that
- *    walks the tile list. It allocates and clears nothing, so it may be captured in a graph and
- *    replayed; every replay recomputes C := alpha*op(A)*op(B) + beta*C for every GEMM.
+ * 3. mdg_dgemm_grouped launches one persistent kernel of `grid` workgroups of 4 waves (0 = 4 per
+ *    CU; rounded up to a multiple of 8, the XCD count) that walks the tile list. It allocates and
+ *    clears nothing, so it may be captured in a graph and replayed; every replay recomputes
+ *    C := alpha*op(A)*op(B) + beta*C for every GEMM.
  * GEMMs must not write overlapping C (not checked).
  * ------------------------------------------------------------------------------------------ */
 
@@ -246,7 +251,8 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc *descs, const int32_t *tile_
 
 /*
  * Runs a plan already in device memory. num_tiles is the value mdg_grouped_plan returned; grid is
- * the number of persistent workgroups (0 = four per CU, never more than num_tiles). Returns 0, or
+ * the number of persistent workgroups (0 = four per CU; capped at num_tiles, then rounded up to a
+ * multiple of 8). Returns 0, or
  * 1 plan NULL or misaligned, 2 num_tiles < 0, 3 grid < 0, or a negative runtime code.
  */
 int mdg_dgemm_grouped(const void *device_plan, int64_t num_tiles, int grid, void *stream);

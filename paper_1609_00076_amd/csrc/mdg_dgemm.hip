@@ -264,16 +264,21 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, dou
     const int64_t ao = a_org + kt * a_step, bo = b_org + kt * b_step;
     load_panel(ma, make_rsrc(g.A + ao, g.ext_a - ao), ra);
     load_panel(mb, make_rsrc(g.B + bo, g.ext_b - bo), rb);
+  };
+  // Panel kt to LDS buffer `buf`; the ragged last panel's k-tail is zeroed here rather than right
+  // after its loads, so that the arithmetic of the panel before it does not wait for them.
+  auto store = [&](int kt, int buf) {
     if (kt == num_k - 1 && k_left_last < C::KT) {  // uniform branch: ragged last panel only
       mask_k_tail(ma, k_left_last, ra);
       mask_k_tail(mb, k_left_last, rb);
     }
+    store_panel(ma, As[buf], ra);
+    store_panel(mb, Bs[buf], rb);
   };
 
   if (num_k > 0) {
     fetch(0);
-    store_panel(ma, As[0], ra);
-    store_panel(mb, Bs[0], rb);
+    store(0, 0);
   }
   __syncthreads();
 
@@ -299,10 +304,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, dou
         for (int bj = 0; bj < C::BN; ++bj)
           acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
     }
-    if (more) {
-      store_panel(ma, As[buf ^ 1], ra);
-      store_panel(mb, Bs[buf ^ 1], rb);
-    }
+    if (more) store(kt + 1, buf ^ 1);
     __syncthreads();
   }
 
@@ -354,6 +356,154 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
     double* c = C + j * ldc + i;
     *c = (beta == 0.0) ? 0.0 : beta * *c;
   }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Wave tiles: one wave computes a 32 x 32 tile of C on its own, with no LDS and no barrier, so
+// every wave of a workgroup (and of a CU) runs its own pipeline over its own list of tiles. This
+// is the tile of the grouped launch's class 2 and of the single-GEMM "wave" variant.
+//
+// Fragments come straight from memory into registers, 16 bytes per lane per load, in k-steps of 8
+// (two MFMA substeps). The MFMA k-index of lane group c (lanes 16c..16c+15) in substep e of step s
+// is 8s + 2c + e, for both operands: the same k-sets in the same order as the ring kernels, so a
+// wave tile returns the ring kernels' bits. The 32 rows of the tile are taken in pairs: lane l
+// feeds rows 2(l%16) and 2(l%16) + 1 (MFMA blocks 0 and 1); the 32 columns likewise. A 16-byte
+// load is then either one row pair (or column pair) at one k -- operands contiguous along m or n
+// -- or a k-pair of one row (column) -- operands contiguous along k -- and four loads per wave
+// cover a step. Lane l ends holding C(i0 + 2(l%16) + bi, j0 + 2(l/16 + 4r) + bj) in register r of
+// block (bi, bj).
+//
+// Loads use buffer resources over the rest of each operand's storage (reads past its end give
+// zero), per-lane 32-bit offsets within a step's panel and a scalar panel origin. Entries with
+// k-index >= k are zero from the bound for operands contiguous along m or n; for operands
+// contiguous along k they are zeroed in registers in the last step.
+// ------------------------------------------------------------------------------------------------
+typedef double d2 __attribute__((ext_vector_type(2)));
+constexpr int kWT = 32;  // rows and columns of a wave tile
+constexpr int kWK = 8;   // k per step
+
+__device__ __forceinline__ d2 load_d2(rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void wave_tile(const GemmArgs& g, int64_t i0, int64_t j0, int lane) {
+  const int r16 = lane & 15, c = lane >> 4;
+  // Per-lane byte offsets within a step's panel. TA: row 2 r16 + u, k-pair 2c; else k = 2c + u,
+  // rows 2 r16 and 2 r16 + 1. TB: k = 2c + u, columns 2 r16, 2 r16 + 1; else column 2 r16 + u,
+  // k-pair 2c.
+  uint32_t offa[2], offb[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    offa[u] = (uint32_t)(8 * (TA ? (int64_t)(2 * r16 + u) * g.lda + 2 * c
+                                 : (int64_t)(2 * c + u) * g.lda + 2 * r16));
+    offb[u] = (uint32_t)(8 * (TB ? (int64_t)(2 * c + u) * g.ldb + 2 * r16
+                                 : (int64_t)(2 * r16 + u) * g.ldb + 2 * c));
+  }
+  const int64_t a_org = TA ? i0 * g.lda : i0;
+  const int64_t a_step = TA ? (int64_t)kWK : (int64_t)kWK * g.lda;
+  const int64_t b_org = TB ? j0 : j0 * g.ldb;
+  const int64_t b_step = TB ? (int64_t)kWK * g.ldb : (int64_t)kWK;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  // alpha == 0 or k == 0: no product (A and B are not read); the epilogue forms beta*C.
+  const int nsteps = (g.alpha == 0.0) ? 0 : (int)((g.k + kWK - 1) / kWK);
+  const int k_last = (int)(g.k - (int64_t)(nsteps - 1) * kWK);  // k-values in the last step
+
+  // Loads of step s.
+  auto load = [&](int s, d2 (&xa)[2], d2 (&xb)[2]) {
+    const int64_t ao = a_org + (int64_t)s * a_step, bo = b_org + (int64_t)s * b_step;
+    const rsrc_t ra = make_rsrc(g.A + ao, g.ext_a - ao);
+    const rsrc_t rb = make_rsrc(g.B + bo, g.ext_b - bo);
+    xa[0] = load_d2(ra, offa[0]);
+    xa[1] = load_d2(ra, offa[1]);
+    xb[0] = load_d2(rb, offb[0]);
+    xb[1] = load_d2(rb, offb[1]);
+  };
+  auto compute = [&](int s, d2 (&xa)[2], d2 (&xb)[2]) {
+    if (s == nsteps - 1 && k_last < kWK) {  // uniform: zero k >= k in k-contiguous operands
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (TA && 2 * c + e >= k_last) xa[u][e] = 0.0;
+          if (!TB && 2 * c + e >= k_last) xb[u][e] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        af[b] = TA ? xa[b][e] : xa[e][b];
+        bf[b] = TB ? xb[e][b] : xb[b][e];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
+    }
+  };
+
+  // Two steps of lookahead over a 3-deep register ring. The steady loop issues its loads
+  // unconditionally (up to two steps past the end: through the buffer bound those read zeros or
+  // other entries of the same storage, and are never used), so every path reaches each compute
+  // with the same loads outstanding and the wait before it stays exact; the last one or two steps
+  // drain without loads.
+  d2 a0[2], b0[2], a1[2], b1[2], a2[2], b2[2];
+  if (nsteps > 0) {
+    load(0, a0, b0);
+    load(1, a1, b1);
+    int s = 0;
+    for (; s + 3 <= nsteps; s += 3) {
+      load(s + 2, a2, b2);
+      compute(s, a0, b0);
+      load(s + 3, a0, b0);
+      compute(s + 1, a1, b1);
+      load(s + 4, a1, b1);
+      compute(s + 2, a2, b2);
+    }
+    if (s < nsteps) compute(s, a0, b0);
+    if (s + 1 < nsteps) compute(s + 1, a1, b1);
+  }
+
+  // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read.
+  const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = j0 + 2 * (c + 4 * r) + bj;
+      if (j >= g.n) continue;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int64_t i = i0 + 2 * r16 + bi;
+        if (i >= g.m) continue;
+        double* cp = g.C + j * g.ldc + i;
+        const double v = alpha * acc[bi][bj][r];
+        *cp = (beta != 0.0) ? v + beta * *cp : v;
+      }
+    }
+}
+
+// Single-GEMM form: a workgroup of 4 waves covers a 64 x 64 tile of C as four independent wave
+// tiles (wave w takes the 32 x 32 quarter (w % 2, w / 2)); tiles are dealt XCD-aware as for the
+// other kernels.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+dgemm_wave_kernel(GemmArgs g, int tiles_m, int tiles_n) {
+  int tm, tn;
+  if (!tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i0 = (int64_t)tm * 64 + kWT * (wave & 1), j0 = (int64_t)tn * 64 + kWT * (wave >> 1);
+  if (i0 >= g.m || j0 >= g.n) return;
+  wave_tile<TA, TB>(g, i0, j0, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -812,26 +962,11 @@ __global__ void __launch_bounds__(256) scale_tri_kernel(int64_t n, int lower, do
 // ------------------------------------------------------------------------------------------------
 // Variant table.
 // ------------------------------------------------------------------------------------------------
-using Big = Cfg<128, 128, 16, 64, 64, 2, 0>;     // 4 waves, each 64x64 (16 MFMA chains)
 using Small = Cfg<64, 64, 16, 32, 32, 4, 0>;     // 4 waves, each 32x32 (4 MFMA chains)
-using Big8a = Cfg<128, 128, 16, 32, 64, 4, 0>;   // 8 waves, each 32x64
-using Big8b = Cfg<128, 128, 16, 64, 32, 4, 0>;   // 8 waves, each 64x32
-using Tall = Cfg<256, 128, 16, 64, 64, 2, 0>;    // 8 waves, each 64x64
-using Wide = Cfg<128, 256, 16, 64, 64, 2, 0>;    // 8 waves, each 64x64
-using Big16 = Cfg<128, 128, 16, 32, 32, 8, 0>;   // 16 waves, each 32x32
-using Tall16 = Cfg<256, 128, 16, 64, 32, 4, 0>;  // 16 waves, each 64x32
 using Mid8 = Cfg<128, 64, 16, 32, 32, 6, 0>;     // 8 waves, each 32x32
-using Big16p = Cfg<128, 128, 16, 32, 32, 8, 1>;  // Big16 with read-friendly LDS padding
-using Small16 = Cfg<64, 64, 16, 16, 16, 8, 1>;   // 16 waves, each 16x16 (one MFMA chain)
-using Skinny = Cfg<64, 64, 16, 32, 32, 4, 1, true>;  // 4 waves of 32x32, old C loaded up front
-using Tiny = Cfg<32, 32, 16, 16, 16, 8, 0>;     // 4 waves, each 16x16 (one MFMA chain)
-using Ring256 = RingCfg<256, 128, 64, 32, 3, 4>;    // 16 waves of 64x32, 3 stages, 1 WG per CU
-using Ring256w = RingCfg<256, 128, 64, 64, 3, 2>;   // 8 waves of 64x64, 3 stages
-using Ring128x4 = RingCfg<128, 128, 32, 32, 4, 4>;  // 16 waves of 32x32, 4 stages
-using Ring128w = RingCfg<128, 256, 32, 64, 3, 4>;   // 16 waves of 32x64, 3 stages
-using Ring256i = RingCfg<256, 128, 64, 32, 3, 4, 1>;    // Ring256, interleaved issue
-using Ring128x4i = RingCfg<128, 128, 32, 32, 4, 4, 1>;  // Ring128x4, interleaved issue
-using Ring128wi = RingCfg<128, 256, 32, 64, 3, 4, 1>;   // Ring128w, interleaved issue
+using Tiny = Cfg<32, 32, 16, 16, 16, 8, 0>;      // 4 waves, each 16x16 (one MFMA chain)
+using Ring256i = RingCfg<256, 128, 64, 32, 3, 4, 1>;    // 16 waves of 64x32, 3 stages, interleaved
+using Ring128x4i = RingCfg<128, 128, 32, 32, 4, 4, 1>;  // 16 waves of 32x32, 4 stages, interleaved
 using Ring256wi = RingCfg<256, 128, 64, 64, 3, 2, 1>;   // 8 waves of 64x64, interleaved issue
 using Ring64s3 = RingCfg<64, 64, 32, 32, 3, 3, 1>;      // 4 waves of 32x32, 3 stages, 3 WGs per CU
 using Ring64s4 = RingCfg<64, 64, 32, 32, 4, 2, 1>;      // 4 stages, 2 WGs per CU
@@ -896,29 +1031,22 @@ constexpr Variant make_variant(const char* name, Eff e, int short_k = 0) {
                   {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
 }
 
+// The single-GEMM form of the wave tiles: 64x64 per workgroup as four independent 32x32 wave
+// tiles, no LDS; 4 workgroups per CU (register-limited).
+constexpr Variant make_wave_variant(const char* name, Eff e, int short_k = 0) {
+  return Variant{name, 64, 64, kWK, 256, 4, {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
+                 {{dgemm_wave_kernel<false, false>, dgemm_wave_kernel<false, true>},
+                  {dgemm_wave_kernel<true, false>, dgemm_wave_kernel<true, true>}}};
+}
+
 // Efficiencies are the measured TFLOP/s of each variant at m = n = k = 8192..16384 divided by
 // 78.6 (per transpose case where given as four numbers, NN NT TN TT).
 const Variant kVariants[] = {
-    make_variant<Big>("mfma_f64_128x128x16_w64x64", 795),
     make_variant<Small>("mfma_f64_64x64x16_w32x32", 760, 360),
-    make_variant<Big8a>("mfma_f64_128x128x16_w32x64", 848),
-    make_variant<Big8b>("mfma_f64_128x128x16_w64x32", 853),
-    make_variant<Tall>("mfma_f64_256x128x16_w64x64", 816),
-    make_variant<Wide>("mfma_f64_128x256x16_w64x64", 816),
-    make_variant<Big16>("mfma_f64_128x128x16_w32x32", 865, 440),
-    make_variant<Tall16>("mfma_f64_256x128x16_w64x32", 847),
     make_variant<Mid8>("mfma_f64_128x64x16_w32x32", 790, 446),
-    make_variant<Big16p>("mfma_f64_128x128x16_w32x32_pad", 860),
-    make_variant<Small16>("mfma_f64_64x64x16_w16x16_pad", 0),
-    make_variant<Skinny>("mfma_f64_64x64x16_w32x32_cpre", 0),
     make_variant<Tiny>("mfma_f64_32x32x16_w16x16", 0),
-    make_ring_variant<Ring256>("ring_f64_256x128x16_w64x32_s3", 893),
-    make_ring_variant<Ring256w>("ring_f64_256x128x16_w64x64_s3", 0),
-    make_ring_variant<Ring128x4>("ring_f64_128x128x16_w32x32_s4", 883),
-    make_ring_variant<Ring128w>("ring_f64_128x256x16_w32x64_s3", 0),
     make_ring_variant<Ring256i>("ring_f64_256x128x16_w64x32_s3_il", Eff(932, 941, 927, 925)),
     make_ring_variant<Ring128x4i>("ring_f64_128x128x16_w32x32_s4_il", Eff(889, 902, 896, 896)),
-    make_ring_variant<Ring128wi>("ring_f64_128x256x16_w32x64_s3_il", 0),
     make_ring_variant<Ring256wi>("ring_f64_256x128x16_w64x64_s3_il", Eff(915, 940, 940, 948)),
     make_ring_variant<Ring64s3>("ring_f64_64x64x16_w32x32_s3_il", Eff(827, 855, 836, 834), 393),
     make_ring_variant<Ring64s4>("ring_f64_64x64x16_w32x32_s4_il", Eff(804, 821, 827, 797)),
@@ -926,6 +1054,7 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x256wi>("ring_f64_128x256x16_w64x64_s3_il", Eff(936, 947, 940, 946)),
     make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(935, 939, 946, 945)),
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
+    make_wave_variant("wave_f64_64x64x8_w32x32", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -960,15 +1089,23 @@ constexpr int kNumSyrkVariants = sizeof(kSyrkVariants) / sizeof(kSyrkVariants[0]
 // Grouped launch: many independent GEMMs in one persistent kernel.
 //
 // A plan (built on the host, copied to the device by the caller) holds one descriptor per GEMM and
-// a list of tiles (gemm, tm, tn) in schedule order. Workgroup w processes list entries
-// w, w + G, w + 2G, ... (G = grid size) and computes each with the same tile code the single-GEMM
-// kernels use: tile class 0 is the 64x64 tile of variant "mfma_f64_64x64x16_w32x32", class 1 the
-// 32x32 tile of "mfma_f64_32x32x16_w16x16". Nothing is allocated or cleared at launch time, so a
-// launch can be captured in a graph and replayed.
+// a list of tiles (gemm, tm, tn) in schedule order. There are two kinds of plan.
+//  - Workgroup tiles (classes 0 and 1): workgroup w processes list entries w, w + G, w + 2G, ...
+//    (G = grid size) with the same tile code the single-GEMM kernels use: class 0 is the 64x64
+//    tile of variant "mfma_f64_64x64x16_w32x32", class 1 the 32x32 tile of
+//    "mfma_f64_32x32x16_w16x16".
+//  - Wave tiles (class 2, every GEMM of the plan): each wave computes 32x32 tiles on its own
+//    (wave_tile, as variant "wave_f64_64x64x8_w32x32"). The host gives every GEMM to one XCD (the
+//    longest first, each to the XCD with the least work so far) and lists each XCD's tiles GEMM by
+//    GEMM; the waves of the workgroups on XCD x walk x's list with a stride of their number, so the
+//    waves working on one GEMM share its panels in that XCD's L2.
+// Nothing is allocated or cleared at launch time, so a launch can be captured in a graph and
+// replayed.
 // ------------------------------------------------------------------------------------------------
 using GroupedCfg0 = Small;
 using GroupedCfg1 = Tiny;
-constexpr int kGroupedClasses = 2;
+constexpr int kGroupedClasses = 3;
+constexpr int kWaveClass = 2;
 constexpr int kGroupedThreads = 256;
 static_assert(GroupedCfg0::THREADS == kGroupedThreads && GroupedCfg1::THREADS == kGroupedThreads,
               "grouped tile classes share one workgroup size");
@@ -981,12 +1118,15 @@ struct GroupedDesc {
 };
 
 struct PlanHeader {
-  int32_t magic, version, count, pad;
+  int32_t magic, version, count, kind;  // kind: 0 workgroup tiles, 1 wave tiles
   int64_t num_tiles;
   int64_t desc_offset, tile_offset;  // bytes from the plan start
   int64_t pad2[3];
 };
 static_assert(sizeof(PlanHeader) == 64, "plan header layout");
+// A wave-tile plan has, right after the header, the tile-list offsets of the 8 XCDs' sublists
+// (int64 [kXcds + 1], entries of the tile list), padded to kXcdTableBytes.
+constexpr int kXcdTableBytes = 80;
 
 constexpr int ilog_max(int a, int b) { return a > b ? a : b; }
 constexpr int kGroupedLds = ilog_max(
@@ -1006,12 +1146,44 @@ __device__ __forceinline__ void grouped_tile(const GroupedDesc& d, int tm, int t
   }
 }
 
+// The waves of workgroup b (on XCD b % 8) walk that XCD's sublist; the host makes the grid a
+// multiple of 8, so each XCD has gridDim.x / 8 workgroups.
+__device__ __forceinline__ void grouped_wave_tiles(const int8_t* plan, const GroupedDesc* descs,
+                                                   const int4* tiles) {
+  const int64_t* xoff = reinterpret_cast<const int64_t*>(plan + sizeof(PlanHeader));
+  const int xcd = blockIdx.x % kXcds;
+  const int per_xcd = gridDim.x / kXcds;
+  const int local = blockIdx.x / kXcds;
+  if (local >= per_xcd) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  constexpr int kWaves = kGroupedThreads / 64;
+  const int64_t stride = (int64_t)per_xcd * kWaves;
+  const int64_t end = xoff[xcd + 1];
+  for (int64_t t = xoff[xcd] + (int64_t)local * kWaves + wave; t < end; t += stride) {
+    const int4 e = tiles[t];
+    const GroupedDesc& d = descs[e.x];
+    const int64_t i0 = (int64_t)e.y * kWT, j0 = (int64_t)e.z * kWT;
+    if (d.ta) {
+      if (d.tb) wave_tile<true, true>(d.g, i0, j0, lane);
+      else      wave_tile<true, false>(d.g, i0, j0, lane);
+    } else {
+      if (d.tb) wave_tile<false, true>(d.g, i0, j0, lane);
+      else      wave_tile<false, false>(d.g, i0, j0, lane);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kGroupedThreads) __attribute__((amdgpu_waves_per_eu(4)))
 grouped_kernel(const int8_t* plan) {
   __shared__ double smem[kGroupedLds];
   const PlanHeader* h = reinterpret_cast<const PlanHeader*>(plan);
   const GroupedDesc* descs = reinterpret_cast<const GroupedDesc*>(plan + h->desc_offset);
   const int4* tiles = reinterpret_cast<const int4*>(plan + h->tile_offset);
+  if (h->kind == 1) {
+    grouped_wave_tiles(plan, descs, tiles);
+    return;
+  }
   const int64_t n = h->num_tiles;
   for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
     const int4 e = tiles[t];
@@ -1029,6 +1201,7 @@ struct GroupedTileRef {
 int grouped_tile_dims(int cls, int* mt, int* nt) {
   if (cls == 0) { *mt = GroupedCfg0::MT; *nt = GroupedCfg0::NT; return 0; }
   if (cls == 1) { *mt = GroupedCfg1::MT; *nt = GroupedCfg1::NT; return 0; }
+  if (cls == kWaveClass) { *mt = kWT; *nt = kWT; return 0; }
   return -1;
 }
 
@@ -1447,15 +1620,26 @@ static int grouped_class_of(const mdg_gemm_desc& d, const int32_t* tile_class, i
 
 int mdg_grouped_tile_classes(void) { return kGroupedClasses; }
 
-int64_t mdg_grouped_plan_bytes(int count, const mdg_gemm_desc* descs, const int32_t* tile_class) {
-  if (count < 0 || (count > 0 && descs == nullptr)) return -1;
-  int64_t tiles = 0;
+// Plan kind for these classes: 0 (classes 0 and 1 only), 1 (class 2 only), -1 (bad or mixed).
+static int grouped_plan_kind(int count, const mdg_gemm_desc* descs, const int32_t* tile_class) {
+  int wave = 0, block = 0;
   for (int i = 0; i < count; ++i) {
     const int cls = grouped_class_of(descs[i], tile_class, i);
     if (cls < 0 || cls >= kGroupedClasses) return -1;
-    tiles += grouped_tiles_of(descs[i], cls);
+    (cls == kWaveClass ? wave : block) += 1;
   }
-  return (int64_t)sizeof(PlanHeader) + (int64_t)count * (int64_t)sizeof(GroupedDesc) + tiles * 16;
+  if (wave && block) return -1;
+  return wave ? 1 : 0;
+}
+
+int64_t mdg_grouped_plan_bytes(int count, const mdg_gemm_desc* descs, const int32_t* tile_class) {
+  if (count < 0 || (count > 0 && descs == nullptr)) return -1;
+  const int kind = grouped_plan_kind(count, descs, tile_class);
+  if (kind < 0) return -1;
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) tiles += grouped_tiles_of(descs[i], grouped_class_of(descs[i], tile_class, i));
+  return (int64_t)sizeof(PlanHeader) + (kind ? kXcdTableBytes : 0) +
+         (int64_t)count * (int64_t)sizeof(GroupedDesc) + tiles * 16;
 }
 
 int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_class,
@@ -1467,10 +1651,12 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_
   const int64_t need = mdg_grouped_plan_bytes(count, descs, tile_class);
   if (need < 0) return 3;
   if (plan == nullptr || plan_bytes < need) return 5;
+  const int kind = grouped_plan_kind(count, descs, tile_class);
   std::vector<GroupedTileRef> refs;
   int8_t* base = static_cast<int8_t*>(plan);
   PlanHeader* h = reinterpret_cast<PlanHeader*>(base);
-  GroupedDesc* gd = reinterpret_cast<GroupedDesc*>(base + sizeof(PlanHeader));
+  GroupedDesc* gd = reinterpret_cast<GroupedDesc*>(base + sizeof(PlanHeader) +
+                                                   (kind ? kXcdTableBytes : 0));
   for (int i = 0; i < count; ++i) {
     const mdg_gemm_desc& d = descs[i];
     const int info = check_args(d.transa, d.transb, d.m, d.n, d.k, d.alpha, d.A, d.lda, d.B, d.ldb,
@@ -1498,7 +1684,8 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_
     o.tiles_n = ntiles ? (int32_t)ceil_div(d.n, nt) : 0;
     if (ntiles && (o.tiles_m > INT32_MAX / 2 || o.tiles_n > INT32_MAX / 2 ||
                    (d.alpha != 0.0 && d.k > 0 &&
-                    !panel_offsets_fit(ta, tb, mt, nt, 16, d.m, d.n, d.k, d.lda, d.ldb)))) {
+                    !panel_offsets_fit(ta, tb, mt, nt, cls == kWaveClass ? kWK : 16, d.m, d.n,
+                                       d.k, d.lda, d.ldb)))) {
       if (bad_index) *bad_index = i;
       return MDG_ERR_SIZE;
     }
@@ -1506,17 +1693,69 @@ int mdg_grouped_plan(int count, const mdg_gemm_desc* descs, const int32_t* tile_
     for (int32_t tn = 0; tn < o.tiles_n; ++tn)
       for (int32_t tm = 0; tm < o.tiles_m; ++tm) refs.push_back(GroupedTileRef{cost, i, tm, tn});
   }
-  if (schedule == MDG_SCHEDULE_LPT)
-    std::stable_sort(refs.begin(), refs.end(),
-                     [](const GroupedTileRef& a, const GroupedTileRef& b) { return a.cost > b.cost; });
+  int64_t xoff[kXcds + 1] = {0};
+  if (kind == 0) {
+    if (schedule == MDG_SCHEDULE_LPT)
+      std::stable_sort(refs.begin(), refs.end(), [](const GroupedTileRef& a, const GroupedTileRef& b) {
+        return a.cost > b.cost;
+      });
+  } else {
+    // Whole GEMMs to XCDs: LPT takes the GEMMs by decreasing total cost and gives each to the XCD
+    // with the least work so far; NATURAL deals them round-robin in order. Each XCD's sublist then
+    // holds its GEMMs in that order, each GEMM's tiles column by column.
+    std::vector<double> gcost(count, 0.0);
+    std::vector<int64_t> gfirst(count, -1), gcount(count, 0);
+    for (size_t t = 0; t < refs.size(); ++t) {
+      const int gi = refs[t].gemm;
+      if (gfirst[gi] < 0) gfirst[gi] = (int64_t)t;
+      gcount[gi] += 1;
+      gcost[gi] += refs[t].cost;
+    }
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    if (schedule == MDG_SCHEDULE_LPT)
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return gcost[a] > gcost[b]; });
+    std::vector<int> owner(count, 0);
+    double load[kXcds] = {0.0};
+    int next = 0;
+    for (int gi : order) {
+      if (gcount[gi] == 0) continue;
+      int x = 0;
+      if (schedule == MDG_SCHEDULE_LPT) {
+        for (int y = 1; y < kXcds; ++y)
+          if (load[y] < load[x]) x = y;
+      } else {
+        x = next;
+        next = (next + 1) % kXcds;
+      }
+      owner[gi] = x;
+      load[x] += gcost[gi];
+    }
+    std::vector<GroupedTileRef> sorted;
+    sorted.reserve(refs.size());
+    for (int x = 0; x < kXcds; ++x) {
+      xoff[x] = (int64_t)sorted.size();
+      for (int gi : order)
+        if (gcount[gi] > 0 && owner[gi] == x)
+          for (int64_t t = 0; t < gcount[gi]; ++t) sorted.push_back(refs[gfirst[gi] + t]);
+    }
+    xoff[kXcds] = (int64_t)sorted.size();
+    refs.swap(sorted);
+  }
   h->magic = kPlanMagic;
-  h->version = 1;
+  h->version = 2;
   h->count = count;
-  h->pad = 0;
+  h->kind = kind;
   h->num_tiles = (int64_t)refs.size();
-  h->desc_offset = (int64_t)sizeof(PlanHeader);
-  h->tile_offset = (int64_t)sizeof(PlanHeader) + (int64_t)count * (int64_t)sizeof(GroupedDesc);
+  h->desc_offset = (int64_t)sizeof(PlanHeader) + (kind ? kXcdTableBytes : 0);
+  h->tile_offset = h->desc_offset + (int64_t)count * (int64_t)sizeof(GroupedDesc);
   h->pad2[0] = h->pad2[1] = h->pad2[2] = 0;
+  if (kind) {
+    int64_t* xt = reinterpret_cast<int64_t*>(base + sizeof(PlanHeader));
+    std::memset(xt, 0, kXcdTableBytes);
+    for (int x = 0; x <= kXcds; ++x) xt[x] = xoff[x];
+  }
   int32_t* tl = reinterpret_cast<int32_t*>(base + h->tile_offset);
   for (size_t t = 0; t < refs.size(); ++t) {
     tl[4 * t + 0] = refs[t].gemm;
@@ -1538,6 +1777,7 @@ int mdg_dgemm_grouped(const void* device_plan, int64_t num_tiles, int grid, void
   if (dc) return dc;
   int64_t g = grid > 0 ? grid : (int64_t)kCUs * 4;
   if (g > num_tiles) g = num_tiles;
+  g = (g + kXcds - 1) / kXcds * kXcds;  // wave-tile plans deal whole workgroups per XCD
   const int8_t* p = static_cast<const int8_t*>(device_plan);
   return launch(reinterpret_cast<const void*>(&grouped_kernel), dim3((unsigned)g),
                 dim3(kGroupedThreads), static_cast<hipStream_t>(stream), p);

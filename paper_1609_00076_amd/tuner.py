@@ -1,8 +1,9 @@
 """Autotuner for grouped dgemm launches: measured search over tile classes, schedules and grids.
 
-A policy is (threshold, schedule, grid): GEMM i uses the 32x32 tile (class 1) when
-min(m_i, n_i) < threshold and the 64x64 tile (class 0) otherwise; the tile list is in natural or
-largest-first (LPT) order; `grid` persistent workgroups walk it. Each candidate is timed as a
+A policy is (tile, threshold, schedule, grid). With workgroup tiles ("block"), GEMM i uses the
+32x32 tile (class 1) when min(m_i, n_i) < threshold and the 64x64 tile (class 0) otherwise; with
+wave tiles ("wave") every GEMM uses class 2. The tile list is in natural or largest-first (LPT)
+order; `grid` persistent workgroups walk it. Each candidate is timed as a
 captured graph of one grouped launch, replayed; the fastest is kept. Results are stored in a JSON
 database keyed by device architecture, HIP version and a workload signature, and read back by
 `best_policy`.
@@ -19,13 +20,17 @@ DB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_db.js
 THRESHOLDS = (0, 40, 64, 96, 160, 1 << 30)
 SCHEDULES = (b.MDG_SCHEDULE_NATURAL, b.MDG_SCHEDULE_LPT)
 GRIDS = (256, 512, 1024, 2048)
-DEFAULT_POLICY = {"threshold": 48, "schedule": b.MDG_SCHEDULE_LPT, "grid": 1024}
+DEFAULT_POLICY = {"tile": "block", "threshold": 48, "schedule": b.MDG_SCHEDULE_LPT, "grid": 1024}
 # Signature of the batched workload: 2048 GEMMs, m, n, k log-uniform in [16, 512].
 GROUPED_SIGNATURE = "grouped|2048|mnk~logU[16,512]|trans iid|tight ld"
 
 
 def classes_for(gemms, policy):
-    """Tile class of each GEMM under `policy` (a policy dict, or a bare threshold)."""
+    """Tile class of each GEMM under `policy` (a policy dict, or a bare threshold): with
+    tile "wave" every GEMM takes the 32x32 wave tile (class 2); otherwise class 1 (32x32
+    workgroup tile) below the min(m, n) threshold and class 0 (64x64) from it on."""
+    if isinstance(policy, dict) and policy.get("tile") == "wave":
+        return [2] * len(gemms)
     threshold = policy["threshold"] if isinstance(policy, dict) else policy
     return [1 if min(g["m"], g["n"]) < threshold else 0 for g in gemms]
 
@@ -61,20 +66,29 @@ def time_policy(gemms, policy, reps=10, warmup=3):
     return e0.elapsed_time(e1) / reps
 
 
+def candidates(thresholds=THRESHOLDS, schedules=SCHEDULES, grids=GRIDS, wave=True):
+    """Policies the tuner times: workgroup tiles for every threshold, schedule and grid, and (with
+    `wave`) the wave tiles for every schedule and grid."""
+    pols = [{"tile": "block", "threshold": th, "schedule": sc, "grid": gr}
+            for th in thresholds for sc in schedules for gr in grids]
+    if wave:
+        pols += [{"tile": "wave", "threshold": 0, "schedule": sc, "grid": gr}
+                 for sc in schedules for gr in grids]
+    return pols
+
+
 def tune_grouped(gemms, signature, thresholds=THRESHOLDS, schedules=SCHEDULES, grids=GRIDS,
-                 reps=10, db_path=DB_PATH, log=None):
-    """Time every candidate policy on `gemms`, store the best under `signature`, return it."""
+                 reps=10, db_path=DB_PATH, log=None, policies=None):
+    """Time every candidate policy on `gemms` (or the given `policies`), store the best under
+    `signature`, return it."""
     results = []
-    for th in thresholds:
-        for sc in schedules:
-            for gr in grids:
-                pol = {"threshold": th, "schedule": sc, "grid": gr}
-                ms = time_policy(gemms, pol, reps=reps)
-                results.append({**pol, "ms": round(ms, 5)})
-                if log:
-                    log(f"[tune] {pol} {ms:.4f} ms")
+    for pol in policies or candidates(thresholds, schedules, grids):
+        ms = time_policy(gemms, pol, reps=reps)
+        results.append({**pol, "ms": round(ms, 5)})
+        if log:
+            log(f"[tune] {pol} {ms:.4f} ms")
     best = min(results, key=lambda r: r["ms"])
-    entry = {"policy": {k: best[k] for k in ("threshold", "schedule", "grid")},
+    entry = {"policy": {k: best[k] for k in ("tile", "threshold", "schedule", "grid")},
              "ms": best["ms"], "candidates": results}
     db = load_db(db_path)
     db[device_key(signature)] = entry

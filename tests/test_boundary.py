@@ -149,6 +149,29 @@ def test_sweep_variant_choice():
             assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"
 
 
+def test_every_variant_is_reachable():
+    """No dead entries in the kernel table: each variant is the automatic choice for some shape and
+    transpose case, a grouped tile class, or a dsyrk configuration."""
+    import numpy as np
+    nv = mdg.mdg_num_variants()
+    sizes = sorted({int(x) for x in np.round(np.logspace(0, 4.3, 60))})
+    chosen = set()
+    for ta in "NT":
+        for tb in "NT":
+            for m in sizes:
+                for n in sizes:
+                    for k in (16, 64, 256, 257, 1024, 2048, 8192):
+                        chosen.add(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
+            for n in sizes:
+                for k in (64, 1024, 8192):
+                    for uplo in "LU":
+                        chosen.add(mdg.mdg_dsyrk_select_variant(uplo, ta, n, k))
+    grouped = {"mfma_f64_64x64x16_w32x32", "mfma_f64_32x32x16_w16x16", "wave_f64_64x64x8_w32x32"}
+    for v in range(nv):
+        name = mdg.mdg_variant_name(v)
+        assert v in chosen or name in grouped, f"variant {v} ({name}) is never used"
+
+
 # ---- level-3 entry points: checks and refusals that return before any HIP call ----------------
 
 FAKE = 0x1000  # a non-NULL address that none of the cases below dereferences
@@ -175,7 +198,7 @@ def test_dsyrk_quick_returns_and_refusals():
     assert _syrk(k=0, beta=1.0, A=None, C=None) == 0
     assert _syrk(variant=mdg.mdg_num_variants()) == -2
     names = [mdg.mdg_variant_name(v) for v in range(mdg.mdg_num_variants())]
-    assert _syrk(variant=names.index("mfma_f64_128x128x16_w64x64")) == -2  # no ring tile
+    assert _syrk(variant=names.index("mfma_f64_64x64x16_w32x32")) == -2  # no ring tile
     # a k-panel of A would span 4 GiB of 32-bit offsets: refused on the host
     assert _syrk(n=4, k=100, lda=600_000_000) == -4
 

@@ -276,7 +276,7 @@ def test_syrk_no_product_and_refusals(uplo):
     assert st == 0 and np.array_equal(got.view(np.uint64), C.view(np.uint64))
     # A GEMM variant without a ring configuration for the update is refused.
     names = [mdg.mdg_variant_name(v) for v in range(mdg.mdg_num_variants())]
-    plain = names.index("mfma_f64_128x128x16_w64x64")
+    plain = names.index("mfma_f64_64x64x16_w32x32")
     st, _ = _run_syrk(plain, uplo, "N", n, 4, 1.0, A, lda, 0.5, C, ldc)
     assert st == -2  # MDG_ERR_VARIANT
     assert mdg.mdg_dsyrk("X", "N", n, 4, 1.0, None, lda, 0.5, None, ldc) == 1

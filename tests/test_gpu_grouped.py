@@ -71,7 +71,8 @@ def _check_against_oracle(probs, gemms, exact):
 
 def _variant_of_class(cls):
     import paper_1609_00076_amd as mdg
-    names = {0: "mfma_f64_64x64x16_w32x32", 1: "mfma_f64_32x32x16_w16x16"}
+    names = {0: "mfma_f64_64x64x16_w32x32", 1: "mfma_f64_32x32x16_w16x16",
+             2: "wave_f64_64x64x8_w32x32"}
     for v in range(mdg.mdg_num_variants()):
         if mdg.mdg_variant_name(v) == names[cls]:
             return v
@@ -99,6 +100,41 @@ def test_grouped_matches_oracle_and_single_launches(dist):
         assert st == 0
         torch.cuda.synchronize()
         assert same_bits(dC.cpu().numpy(), g["C"].cpu().numpy())
+
+
+@pytest.mark.parametrize("dist", ["uniform", "int"])
+def test_wave_plan_matches_oracle_and_single_launches(dist):
+    """Class 2 (every GEMM on 32x32 wave tiles): each GEMM matches the oracle (bit-exact on
+    integers), and is bitwise the single-GEMM wave variant's result and a ring variant's (the same
+    k-order), on the default grid and on grids that make waves walk many tiles."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    from paper_1609_00076_amd.grouped import GroupedPlan
+    probs = _batch(5 if dist == "uniform" else 6, 150, 1, 300, dist=dist, special=True)
+    ring = [v for v in range(mdg.mdg_num_variants())
+            if mdg.mdg_variant_name(v) == "ring_f64_128x64x16_w32x32_s3_il"][0]
+    alone = {}
+    for name, v in (("wave", _variant_of_class(2)), ("ring", ring)):
+        outs = []
+        for p in probs:
+            dA, dB = torch.from_numpy(p["A"]).cuda(), torch.from_numpy(p["B"]).cuda()
+            dC = torch.from_numpy(p["C"]).cuda()
+            assert mdg.mdg_dgemm_ex(v, p["transa"], p["transb"], p["m"], p["n"], p["k"],
+                                    p["alpha"], dA, p["lda"], dB, p["ldb"], p["beta"], dC,
+                                    p["ldc"]) == 0
+            outs.append(dC)
+        torch.cuda.synchronize()
+        alone[name] = [o.cpu().numpy() for o in outs]
+    for sched, grid in ((mdg.MDG_SCHEDULE_LPT, 0), (mdg.MDG_SCHEDULE_NATURAL, 8),
+                        (mdg.MDG_SCHEDULE_LPT, 24)):
+        gemms = _to_device(probs)
+        GroupedPlan(gemms, [2] * len(gemms), sched).launch(grid)
+        torch.cuda.synchronize()
+        _check_against_oracle(probs, gemms, exact=(dist == "int"))
+        for i, g in enumerate(gemms):
+            got = g["C"].cpu().numpy()
+            assert same_bits(got, alone["wave"][i]), f"GEMM {i}: grouped vs single wave launch"
+            assert same_bits(got, alone["ring"][i]), f"GEMM {i}: grouped vs ring variant"
 
 
 def test_schedules_and_grids_agree_bitwise():
@@ -161,10 +197,10 @@ def test_full_batch_graph_replays_match_oracle():
     refs = [run_oracle(p, p["alpha"], p["beta"]) for p in probs]
     gemms = _to_device(probs)
     c0 = [g["C"].clone() for g in gemms]
-    policy = tuner.best_policy(tuner.GROUPED_SIGNATURE)
-    classes = tuner.classes_for(gemms, policy)
-    for grid in (policy["grid"], 0):
-        plan = GroupedPlan(gemms, classes, policy["schedule"])
+    tuned = tuner.best_policy(tuner.GROUPED_SIGNATURE)
+    wave = {"tile": "wave", "threshold": 0, "schedule": 1, "grid": 0}
+    for policy, grid in ((tuned, tuned["grid"]), (tuned, 0), (wave, 0)):
+        plan = GroupedPlan(gemms, tuner.classes_for(gemms, policy), policy["schedule"])
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
@@ -179,8 +215,8 @@ def test_full_batch_graph_replays_match_oracle():
             torch.cuda.synchronize()
             graph.replay()
             torch.cuda.synchronize()
-            print(f"[grouped] 2048-GEMM batch, grid {grid}, replay {replay}: checking",
-                  flush=True)
+            print(f"[grouped] 2048-GEMM batch, policy {policy}, grid {grid}, replay {replay}: "
+                  "checking", flush=True)
             worst = 0.0
             for i, (p, g, (ref, D)) in enumerate(zip(probs, gemms, refs)):
                 got = g["C"].cpu().numpy()

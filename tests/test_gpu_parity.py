@@ -216,11 +216,11 @@ def test_transposed_problem_gives_transposed_result_bitwise(variant):
     assert same_bits(r1, r2), f"variant {variant}"
 
 
-@pytest.mark.parametrize("family", ["ring_", "mfma_"])
+@pytest.mark.parametrize("family", [("ring_", "wave_"), ("mfma_",)])
 @pytest.mark.parametrize("trans", TRANS)
 def test_variant_family_agrees_bitwise_on_float_data(trans, family):
     """Within a kernel family every variant sums each entry's products in the same k-order (ring
-    kernels: 16-deep panels in order, k-index 8h + 2c + e within a panel; register-staged kernels:
+    and wave kernels: MFMA k-sets {8s + 2c + e} in order of s and e; register-staged kernels:
     4-deep MFMA steps in order), whatever the tile, wave layout or fragment read; so on
     Uniform[-1,1] data all variants of a family return the same bits."""
     import paper_1609_00076_amd as mdg

@@ -25,9 +25,9 @@ def _plan(descs, classes=None, schedule=mdg.MDG_SCHEDULE_LPT):
     return st, nt, bad, buf
 
 
-def _tiles(buf):
-    magic, version, count, _, ntiles, doff, toff = struct.unpack_from("<iiiiqqq", buf, 0)
-    assert magic == 0x4D444750 and version == 1
+def _tiles(buf, kind=0):
+    magic, version, count, k, ntiles, doff, toff = struct.unpack_from("<iiiiqqq", buf, 0)
+    assert magic == 0x4D444750 and version == 2 and k == kind
     return count, np.frombuffer(buf[toff:toff + 16 * ntiles], dtype=np.int32).reshape(-1, 4), doff
 
 
@@ -106,4 +106,60 @@ def test_launch_argument_checks_return_before_any_device_call():
     assert mdg.mdg_dgemm_grouped(FAKE, -1) == 2
     assert mdg.mdg_dgemm_grouped(FAKE, 5, grid=-3) == 3
     assert mdg.mdg_dgemm_grouped(FAKE, 0) == 0
-    assert mdg.mdg_grouped_tile_classes() == 2
+    assert mdg.mdg_grouped_tile_classes() == 3
+
+
+def _wave_batch(count=90, seed=3):
+    rng = np.random.default_rng(seed)
+    descs = []
+    for _ in range(count):
+        m, n, k = (int(x) for x in rng.integers(1, 400, 3))
+        descs.append(_desc("NT"[rng.integers(2)], "NT"[rng.integers(2)], m, n, k))
+    return descs
+
+
+@pytest.mark.parametrize("schedule", [mdg.MDG_SCHEDULE_LPT, mdg.MDG_SCHEDULE_NATURAL])
+def test_wave_plan_xcd_sublists(schedule):
+    """Wave-tile plans (class 2 for every GEMM): every 32x32 tile exactly once; the tile list is cut
+    into 8 XCD sublists (offsets after the header), each GEMM wholly in one sublist with its tiles
+    contiguous and column by column; LPT gives GEMMs to XCDs by decreasing cost to the least loaded
+    one (so no XCD ends with more than the lightest plus the largest GEMM), NATURAL round-robin."""
+    descs = _wave_batch()
+    st, nt, bad, buf = _plan(descs, [2] * len(descs), schedule)
+    assert st == 0 and bad == -1
+    count, tiles, doff = _tiles(buf, kind=1)
+    assert doff == 64 + 80
+    xoff = struct.unpack_from("<9q", buf, 64)
+    assert xoff[0] == 0 and xoff[8] == nt == len(tiles) and list(xoff) == sorted(xoff)
+    want = {(i, tm, tn) for i, d in enumerate(descs)
+            for tn in range(-(-d.n // 32)) for tm in range(-(-d.m // 32))}
+    got = [tuple(int(x) for x in row[:3]) for row in tiles]
+    assert len(got) == len(set(got)) and set(got) == want
+    owner, load = {}, [0.0] * 8
+    for x in range(8):
+        sub = got[xoff[x]:xoff[x + 1]]
+        seen = []
+        for g, tm, tn in sub:
+            assert owner.setdefault(g, x) == x, "a GEMM split over XCDs"
+            if not seen or seen[-1] != g:
+                assert g not in seen, "a GEMM's tiles not contiguous"
+                seen.append(g)
+        for g in seen:
+            gt = [(tm, tn) for gg, tm, tn in sub if gg == g]
+            assert gt == sorted(gt, key=lambda t: (t[1], t[0])), "column by column"
+            load[x] += len(gt) * 32 * 32 * descs[g].k
+    cost = {g: -(-descs[g].m // 32) * -(-descs[g].n // 32) * 1024 * descs[g].k for g in owner}
+    if schedule == mdg.MDG_SCHEDULE_LPT:
+        assert max(load) - min(load) <= max(cost.values())
+    else:
+        assert all(owner[g] == i % 8 for i, g in enumerate(sorted(owner)))
+
+
+def test_wave_class_cannot_mix_with_workgroup_classes():
+    descs = _wave_batch(10)
+    assert mdg.mdg_grouped_plan_bytes(descs, [2] * 9 + [0]) == -1
+    buf = np.zeros(1 << 16, dtype=np.uint8)
+    assert mdg.mdg_grouped_plan(descs, [2] * 9 + [1], mdg.MDG_SCHEDULE_LPT, buf)[0] == 3
+    n0 = mdg.mdg_grouped_plan_bytes(descs, [2] * 10)
+    tiles = sum(-(-d.m // 32) * -(-d.n // 32) for d in descs)
+    assert n0 == 64 + 80 + 10 * 136 + 16 * tiles  # 136-byte descriptors

@@ -194,6 +194,67 @@ int mdg_dgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int6
                             int nslices, void *stream);
 
 /* ------------------------------------------------------------------------------------------
+ * Split-precision FP64 GEMM by the Chinese remainder theorem (Ozaki scheme II: Ozaki, Uchino and
+ * Imamura 2025; the same operation of section 1.2, emulated).
+ *
+ * op(A) is scaled row by row and op(B) column by column to integers of w bits
+ * (A'(i,p) = trunc(A(i,p) 2^(w - e_i)), e_i the binary exponent of the row maximum). For each of
+ * `nmoduli` pairwise coprime moduli m_l (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211,
+ * 199, 197, 193, 191, 181, 179, 173, 167, 163, 157, 151, 149, in this order) the symmetric int8
+ * residues of A' and B' are multiplied exactly in INT32 on the INT8 matrix cores
+ * (v_mfma_i32_32x32x32_i8) and reduced modulo m_l; the Chinese remainder theorem turns the residues
+ * into the integer (A'B')(i,j) exactly, since w is the largest width (at most 72) with
+ * 4 k 2^(2w) <= M = prod m_l; that integer is rounded once to binary64, unscaled, and combined with
+ * alpha, beta and the old C in binary64. One INT8 product per modulus, against s(s+1)/2 slice
+ * products for mdg_dgemm_split. The error comes from the w-bit scaling alone: measured on
+ * u * 2^e data with e uniform in [-phi, phi], nmoduli = 14 (phi = 0), 15 (phi = 8), 16 (phi = 32)
+ * keep max |C - Cref| / (|A||B|)_ij below 1e-13 at k = 2048 to 8192; at k = 32, phi = 8 needs 16.
+ * Non-finite inputs: as mdg_dgemm_split (a row of op(A) or column of op(B) holding NaN or Inf makes
+ * that row or column of C NaN).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Largest supported `nmoduli` (the smallest is 1). */
+int mdg_crt_max_moduli(void);
+
+/* The width w (bits) the CRT path scales op(A) and op(B) to for this k and modulus count, or 0
+ * if nmoduli is out of range (or too small for any width). Host only. */
+int mdg_crt_bits(int64_t k, int nmoduli);
+
+/*
+ * Bytes of device workspace mdg_dgemm_crt needs, or -1 for invalid sizes or modulus count.
+ * Layout (each part aligned to 256 bytes): the int8 residues of op(A) (rows = m) and op(B)^T
+ * (rows = n) in the k-panel layout of mdg_split_slices (slice l = modulus l), the product residues
+ * (nmoduli x m x ceil(n/4) 32-bit words: word (j/4)*m + i of modulus l holds the residues of
+ * C(i, 4(j/4) .. 4(j/4)+3), one byte each), then int32 exponents of the m rows and n columns.
+ */
+int64_t mdg_dgemm_crt_workspace_size(int64_t m, int64_t n, int64_t k, int nmoduli);
+
+/*
+ * C := alpha*op(A)*op(B) + beta*C by the CRT scheme above. Arguments 1-13 and the stream are as
+ * for mdg_dgemm; `workspace` is a caller-owned device buffer of at least
+ * mdg_dgemm_crt_workspace_size(m, n, k, nmoduli) bytes, 256-byte aligned, which the call
+ * overwrites. Extra status codes: 14 nmoduli out of range (or too few for this k), 15 workspace
+ * NULL, too small or misaligned; MDG_ERR_SIZE when one modulus' residues of an operand exceed
+ * 4 GiB. Conventions for m, n, k, alpha, beta zero are those of mdg_dgemm.
+ */
+int mdg_dgemm_crt(char transa, char transb, int64_t m, int64_t n, int64_t k,
+                  double alpha, const double *A, int64_t lda,
+                  const double *B, int64_t ldb,
+                  double beta, double *C, int64_t ldc,
+                  int nmoduli, void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
+ * The residue step alone, for one operand (operand, trans, rows, k, X, ld as for
+ * mdg_split_slices): writes the symmetric residues of the `bits`-wide scaled integers modulo the
+ * first nmoduli moduli, residue l of entry (r, p) at the byte mdg_split_slices gives slice l, and
+ * the exponents (0x7FFFFFFF for a row holding NaN or Inf, whose residues are then zero). Returns 0,
+ * or 1 operand, 2 trans, 3 rows < 0, 4 k < 0, 5 X NULL, 6 ld too small, 7 nmoduli out of range,
+ * 8 bits outside 1..72, 9 output NULL, or a negative runtime code.
+ */
+int mdg_crt_residues(int operand, char trans, int64_t rows, int64_t k, const double *X, int64_t ld,
+                     int nmoduli, int bits, int8_t *residues, int32_t *exponents, void *stream);
+
+/* ------------------------------------------------------------------------------------------
  * Grouped launch: many independent dgemm operations (each exactly as mdg_dgemm) in one
  * persistent kernel. Not in the paper; a batching layer over the same operation.
  *

@@ -101,6 +101,16 @@ def load():
     lib.mdg_dgemm_split_noalloc.restype = ci
     lib.mdg_dgemm_split_noalloc_max_bytes.argtypes = []
     lib.mdg_dgemm_split_noalloc_max_bytes.restype = i64
+    lib.mdg_crt_max_moduli.argtypes = []
+    lib.mdg_crt_max_moduli.restype = ci
+    lib.mdg_crt_bits.argtypes = [i64, ci]
+    lib.mdg_crt_bits.restype = ci
+    lib.mdg_dgemm_crt_workspace_size.argtypes = [i64, i64, i64, ci]
+    lib.mdg_dgemm_crt_workspace_size.restype = i64
+    lib.mdg_dgemm_crt.argtypes = gemm_args[:-1] + [ci, vp, i64, vp]
+    lib.mdg_dgemm_crt.restype = ci
+    lib.mdg_crt_residues.argtypes = [ci, ch, i64, i64, vp, i64, ci, ci, vp, vp, vp]
+    lib.mdg_crt_residues.restype = ci
     lib.mdg_split_slices.argtypes = [ci, ch, i64, i64, vp, i64, ci, vp, vp, vp]
     lib.mdg_split_slices.restype = ci
     dptr = ctypes.POINTER(mdg_gemm_desc)
@@ -343,6 +353,43 @@ def mdg_split_slices(operand, trans, rows, k, X, ld, nslices, slices, exponents,
     ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
     return load().mdg_split_slices(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),
                                    int(nslices), sp, ep, _stream(stream))
+
+
+def mdg_crt_max_moduli() -> int:
+    return load().mdg_crt_max_moduli()
+
+
+def mdg_crt_bits(k, nmoduli) -> int:
+    return load().mdg_crt_bits(int(k), int(nmoduli))
+
+
+def mdg_dgemm_crt_workspace_size(m, n, k, nmoduli) -> int:
+    return load().mdg_dgemm_crt_workspace_size(int(m), int(n), int(k), int(nmoduli))
+
+
+def mdg_dgemm_crt(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nmoduli,
+                  workspace, workspace_bytes, stream=None) -> int:
+    """Split-precision C := alpha*op(A)*op(B) + beta*C by the Chinese remainder theorem on INT8
+    MFMA; `workspace` is a device tensor (any dtype) or address of at least `workspace_bytes`."""
+    args = _marshal(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
+    ws = _raw_ptr(workspace, max(0, int(workspace_bytes)), "workspace")
+    return load().mdg_dgemm_crt(*args[:-1], int(nmoduli), ws, int(workspace_bytes), args[-1])
+
+
+def mdg_crt_residues(operand, trans, rows, k, X, ld, nmoduli, bits, residues, exponents,
+                     stream=None) -> int:
+    """The residue step alone for one operand (layout as mdg_split_slices, slice l = modulus l)."""
+    kp = (int(k) + 63) // 64 * 64
+    row_contig = _is_trans(trans) if operand == 0 else not _is_trans(trans)
+    need_x = _extent(k if row_contig else rows, rows if row_contig else k, ld) \
+        if rows > 0 and k > 0 and ld >= max(1, k if row_contig else rows) else 0
+    ok_n = 1 <= int(nmoduli) <= mdg_crt_max_moduli()
+    xp = _ptr(X, need_x, "X")
+    rp = (int(rows) + 127) // 128 * 128
+    rsp = _raw_ptr(residues, int(nmoduli) * rp * kp if ok_n and rows > 0 else 0, "residues")
+    ep = _raw_ptr(exponents, 4 * int(rows) if rows > 0 else 0, "exponents")
+    return load().mdg_crt_residues(int(operand), _ch(trans), int(rows), int(k), xp, int(ld),
+                                   int(nmoduli), int(bits), rsp, ep, _stream(stream))
 
 
 def mdg_grouped_tile_classes() -> int:

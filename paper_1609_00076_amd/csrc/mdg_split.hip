@@ -19,6 +19,7 @@
 // with zeros to multiples of 128 rows and 64 k-values.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <mutex>
 #include <type_traits>
 
@@ -657,6 +658,433 @@ split_gemm32_kernel(SplitArgs g, int tiles_m, int tiles_n) {
   split32_tile<S>(g, tiles_m, tiles_n, lds);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Split precision by the Chinese remainder theorem (Ozaki scheme II: Ozaki, Uchino, Imamura 2025).
+//
+//   1. op(A) row i is scaled to integers of w bits, A'(i,p) = trunc(A(i,p) 2^(w - e_i)), e_i the
+//      row maximum's exponent as for the slices (|A'| < 2^w); op(B) column j likewise.
+//   2. For each of N pairwise coprime moduli m_l <= 256, the symmetric residues a_l = A' mod m_l
+//      and b_l = B' mod m_l lie in [-128, 127] and are stored as int8 "slices" in the same k-panel
+//      layout as the slices above (slice l = modulus l).
+//   3. P_l = a_l b_l is formed exactly in INT32 on v_mfma_i32_32x32x32_i8 (|P_l| <= k 2^14, folded
+//      modulo m_l when k would overflow it) and reduced to r_l = P_l mod m_l in [0, m_l).
+//   4. X = sum_l r_l W_l mod M, W_l = (M/m_l) ((M/m_l)^-1 mod m_l), M = prod m_l, taken in
+//      (-M/2, M/2]: with 4 k 2^(2w) <= M this is the integer (A'B')(i,j) exactly.
+//   5. C := alpha RN(X) 2^(e_i + f_j - 2w) + beta C, RN the rounding of the integer X to binary64.
+// N products replace the S(S+1)/2 of the slices for the same accuracy.
+// ------------------------------------------------------------------------------------------------
+constexpr int kMaxModuli = 24;
+constexpr int kCrtMaxBits = 72;
+constexpr int kLimbs = 7;  // 32-bit limbs of the integers below 2^224 that step 4 forms
+__constant__ int c_moduli[kMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211,
+                                         199, 197, 193, 191, 181, 179, 173, 167, 163, 157, 151, 149};
+constexpr int kModuliHost[kMaxModuli] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211,
+                                         199, 197, 193, 191, 181, 179, 173, 167, 163, 157, 151, 149};
+
+// v mod m for 0 <= v < 2^24 and 2 <= m <= 256 (inv = 1/m in float): the float quotient is the true
+// one or one less, so one correction each way makes the remainder exact.
+__device__ __forceinline__ int mod_small(int v, int m, float inv) {
+  int r = v - (int)((float)v * inv) * m;
+  r += (r < 0) ? m : 0;
+  r -= (r >= m) ? m : 0;
+  return r;
+}
+
+// Residues of 16 scaled entries (already integers of at most 72 bits held in binary64) for one
+// modulus, as 16 int8 bytes in the symmetric range. Each |a| splits exactly into three 24-bit
+// parts, a = a2 2^48 + a1 2^24 + a0, reduced separately.
+struct Parts16 {
+  int p0[16], p1[16], p2[16];
+  bool neg[16];
+};
+
+__device__ __forceinline__ void split_parts(const double (&a)[16], Parts16& q) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const double x = fabs(a[e]);
+    const double h2 = floor(ldexp(x, -48));
+    const double rem = x - ldexp(h2, 48);
+    const double h1 = floor(ldexp(rem, -24));
+    q.p2[e] = (int)h2;
+    q.p1[e] = (int)h1;
+    q.p0[e] = (int)(rem - ldexp(h1, 24));
+    q.neg[e] = a[e] < 0.0;
+  }
+}
+
+__device__ __forceinline__ v4i residues16(const Parts16& q, int m) {
+  const float inv = 1.0f / (float)m;
+  const int c24 = mod_small(1 << 23, m, inv) * 2 % m;  // 2^24 mod m
+  const int c48 = mod_small(c24 * c24, m, inv);         // 2^48 mod m
+  const int half = m - m / 2;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    int r = mod_small(mod_small(q.p2[e], m, inv) * c48 + mod_small(q.p1[e], m, inv) * c24 +
+                          mod_small(q.p0[e], m, inv),
+                      m, inv);
+    if (q.neg[e] && r != 0) r = m - r;
+    if (r >= half) r -= m;
+    w[e / 4] |= ((uint32_t)r & 0xFFu) << (8 * (e % 4));
+  }
+  return (v4i){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+}
+
+// Step 2 for one operand: one 64 x 64 block (rows x k) per workgroup, staged through LDS as for the
+// slices; thread t scales row t/4, k-values 16 (t%4) .. +15, and writes their residues for every
+// modulus. Rows with a non-finite entry (flagged by the exponent pass) get zero residues.
+template <bool ROW_CONTIG>
+__global__ void __launch_bounds__(256) crt_residue_kernel(const double* X, int64_t ld, int64_t rows,
+                                                          int64_t k, int64_t kp, int nmod, int bits,
+                                                          int8_t* out, const int32_t* enc) {
+  __shared__ double tile[64][65];
+  const int t = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * 64, p0 = (int64_t)blockIdx.y * 64;
+  const int64_t rp = round128(rows);
+  if (!ROW_CONTIG) {
+    const int r = t & 63;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int pp = (t >> 6) + 4 * i;
+      tile[r][pp] = (row0 + r < rows && p0 + pp < k) ? X[(p0 + pp) * ld + row0 + r] : 0.0;
+    }
+  } else {
+    const int pp = t & 63;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = (t >> 6) + 4 * i;
+      tile[r][pp] = (row0 + r < rows && p0 + pp < k) ? X[(row0 + r) * ld + p0 + pp] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int r = t >> 2, q0 = 16 * (t & 3);
+  const int enc_r = (row0 + r < rows) ? enc[row0 + r] : 0;
+  const bool finite = enc_r != kNonFinite;
+  const int e = finite ? decode_exponent(enc_r) : 0;
+  double a[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = finite ? trunc(ldexp(tile[r][q0 + i], bits - e)) : 0.0;
+  Parts16 q;
+  split_parts(a, q);
+  for (int l = 0; l < nmod; ++l)
+    *reinterpret_cast<v4i*>(out + slice_offset(l, row0 + r, p0 + q0, rp, kp)) =
+        residues16(q, c_moduli[l]);
+}
+
+// Step 3: the modular products. Workgroup: one modulus l and one 256 x 128 tile of C, 8 waves
+// (4 x 2) of 64 x 64, each 2 x 2 blocks of v_mfma_i32_32x32x32_i8 (lane layout as in
+// split32_tile). The 32-deep k-steps go through a ring of 3 LDS stages of 12 chunks (8 of A, 4 of
+// B), filled by direct loads two steps ahead. At the end each lane reduces its accumulators
+// modulo m_l and writes them, four columns to a 32-bit word, to R_l[(j/4) m + i] (R_l holds
+// m * ceil(n/4) words). Workgroups are ordered modulus-major, so each XCD works on one or two
+// moduli at a time and their residue slices stay in its L2 and the Infinity Cache.
+constexpr int kCrtMT = 256, kCrtNT = 128, kCrtKStep = 32, kCrtStages = 3;
+constexpr int kCrtACh = kCrtMT / 32, kCrtBCh = kCrtNT / 32, kCrtCh = kCrtACh + kCrtBCh;
+constexpr int kCrtLoads = (kCrtCh + 7) / 8;         // direct loads per wave per stage
+constexpr int kCrtStage = kCrtCh * kChunk;
+constexpr int kCrtLds = kCrtStages * kCrtStage + kChunk;  // + a trash chunk for idle loads
+
+struct CrtArgs {
+  int64_t m, n, kp;
+  const int8_t* As;  // residues of op(A), rows rounded to 128 (slice_offset layout)
+  const int8_t* Bs;  // residues of op(B)^T
+  uint32_t* R;       // product residues
+  int nmod;
+  int fold_steps;    // k-steps after which the accumulators are reduced modulo m_l
+};
+
+__device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int tiles_n,
+                                              int8_t* lds) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave_m = wave & 3, wave_n = wave >> 2;
+
+  // XCD-aware order over (modulus, tile): each XCD a contiguous run, modulus-major, tiles in
+  // column groups of 4 tile-rows. The host rounds the grid up to a multiple of 8.
+  const int nwg = gridDim.x;
+  const int v = (blockIdx.x % 8) * (nwg / 8) + blockIdx.x / 8;
+  const int tiles = tiles_m * tiles_n;
+  if (v >= tiles * g.nmod) return;
+  // (the integer divisions run on the vector unit; readfirstlane keeps the results scalar)
+  const int l = __builtin_amdgcn_readfirstlane(v / tiles), t = v - l * tiles;
+  constexpr int kGroup = 4;
+  const int per_group = kGroup * tiles_n;
+  const int grp = t / per_group, first_m = grp * kGroup;
+  const int gsize = min(tiles_m - first_m, kGroup);
+  const int rem = t - grp * per_group;
+  const int tm = __builtin_amdgcn_readfirstlane(first_m + rem % gsize);
+  const int tn = __builtin_amdgcn_readfirstlane(rem / gsize);
+  const int64_t row0 = (int64_t)tm * kCrtMT, col0 = (int64_t)tn * kCrtNT;
+  const int m_l = c_moduli[l];
+
+  const int64_t rpa = round128(g.m), rpb = round128(g.n);
+  const int64_t slice_a = rpa * g.kp, slice_b = rpb * g.kp;
+  const int8_t* a_base = g.As + l * slice_a;
+  const int8_t* b_base = g.Bs + l * slice_b;
+  const int nsteps = (int)(g.kp / kCrtKStep);  // >= 2: kp is a positive multiple of 64
+
+  // Direct load u of wave w moves chunk c = 8u + w: c < 8 is rows 32c.. of A, c < 12 rows
+  // 32(c - 8).. of B, the rest idle (an empty buffer into the trash chunk).
+  uint32_t voff[kCrtLoads];
+#pragma unroll
+  for (int u = 0; u < kCrtLoads; ++u) {
+    const int c = 8 * u + wave;
+    int64_t o = 0;
+    if (c < kCrtACh) o = (row0 + 32 * c) * kCrtKStep;
+    else if (c < kCrtCh) o = (col0 + 32 * (c - kCrtACh)) * kCrtKStep;
+    voff[u] = (uint32_t)o + 16u * (uint32_t)lane;
+  }
+  auto issue = [&](int ks) __attribute__((always_inline)) {
+    int8_t* st = lds + (ks % kCrtStages) * kCrtStage;
+#pragma unroll
+    for (int u = 0; u < kCrtLoads; ++u) {
+      const int c = 8 * u + wave;
+      const bool is_a = c < kCrtACh, is_b = !is_a && c < kCrtCh;
+      const int8_t* base = is_b ? b_base : a_base;
+      const int64_t bytes = is_a ? slice_a : is_b ? slice_b : 0;
+      const uint32_t soff = is_a ? (uint32_t)ks * (uint32_t)(rpa * kCrtKStep)
+                                 : is_b ? (uint32_t)ks * (uint32_t)(rpb * kCrtKStep) : 0u;
+      int8_t* dst = (is_a || is_b) ? st + c * kChunk : lds + kCrtStages * kCrtStage;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(make_rsrc(base, bytes), (lds_void_ptr)dst, 16,
+                                               voff[u], (int)soff, 0, 0);
+    }
+  };
+
+  const int frag = 16 * row_slot(lane & 31, lane >> 5);
+  const int a_frag = 2 * wave_m * kChunk + frag;               // + bi KiB
+  const int b_frag = (kCrtACh + 2 * wave_n) * kChunk + frag;   // + bj KiB
+  v4i af[2], bf[2];
+  auto read = [&](int ks) __attribute__((always_inline)) {
+    const int8_t* st = lds + (ks % kCrtStages) * kCrtStage;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      af[b] = *reinterpret_cast<const v4i*>(st + a_frag + b * kChunk);
+      bf[b] = *reinterpret_cast<const v4i*>(st + b_frag + b * kChunk);
+    }
+  };
+
+  v16i acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
+  // acc := acc mod m_l (in [0, m_l)), exact for |acc| < 2^31 and m_l >= 128: the float quotient
+  // is within two of the truth (v rounds to 24 bits, then the product once), so two corrections
+  // each way make the remainder exact.
+  const float inv = 1.0f / (float)m_l;
+  auto reduce = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int vv = acc[bi][bj][r];
+          int x = vv - (int)((float)vv * inv) * m_l;
+          x += (x < 0) ? m_l : 0;
+          x += (x < 0) ? m_l : 0;
+          x -= (x >= m_l) ? m_l : 0;
+          x -= (x >= m_l) ? m_l : 0;
+          acc[bi][bj][r] = x;
+        }
+  };
+  auto mfma = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
+  };
+
+  const int pre = nsteps < kCrtStages ? nsteps : kCrtStages;
+  for (int ks = 0; ks < pre; ++ks) issue(ks);
+  if (pre == 3) wait_vm_lgkm0<2 * kCrtLoads>();
+  else wait_vm_lgkm0<kCrtLoads>();  // two steps issued, the first has landed
+  bare_barrier();
+  read(0);
+  // Steady state: the fragments of step ks are in registers. Multiply, wait for step ks + 1's
+  // loads, barrier (every wave has read step ks), refill ks's stage with step ks + 3, read ks + 1.
+  int ks = 0, since_fold = 0;
+  for (; ks + 3 < nsteps; ++ks) {
+    mfma();
+    wait_vm_lgkm0<kCrtLoads>();
+    bare_barrier();
+    issue(ks + 3);
+    read(ks + 1);
+    if (++since_fold == g.fold_steps) {  // uniform; only when k exceeds 2^17
+      reduce();
+      since_fold = 0;
+    }
+  }
+  for (; ks + 1 < nsteps; ++ks) {  // drain: no loads left to issue
+    mfma();
+    if (ks + 2 < nsteps) wait_vm_lgkm0<kCrtLoads>();
+    else wait_vm_lgkm0<0>();
+    bare_barrier();
+    read(ks + 1);
+  }
+  mfma();
+  reduce();
+
+  const int64_t words_n = (g.n + 3) / 4;
+  uint32_t* R = g.R + (int64_t)l * g.m * words_n;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi) {
+    const int64_t i = row0 + 64 * wave_m + 32 * bi + (lane & 31);
+    if (i >= g.m) continue;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t j = col0 + 64 * wave_n + 32 * bj + 8 * q + 4 * (lane >> 5);
+        if (j >= g.n) continue;
+        const uint32_t word = (uint32_t)acc[bi][bj][4 * q] |
+                              ((uint32_t)acc[bi][bj][4 * q + 1] << 8) |
+                              ((uint32_t)acc[bi][bj][4 * q + 2] << 16) |
+                              ((uint32_t)acc[bi][bj][4 * q + 3] << 24);
+        R[(j >> 2) * g.m + i] = word;
+      }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
+crt_gemm_kernel(CrtArgs g, int tiles_m, int tiles_n) {
+  __shared__ __attribute__((aligned(1024))) int8_t lds[kCrtLds];
+  crt_gemm_tile(g, tiles_m, tiles_n, lds);
+}
+
+// Step 4 and 5 constants, computed on the host for the call's modulus count.
+struct CrtConst {
+  uint32_t W[kMaxModuli][kLimbs];  // W_l
+  uint32_t M[kLimbs];
+  uint32_t half[kLimbs];           // M / 2
+  double Mf;                       // M rounded to binary64
+  int nmod, bits;
+};
+
+struct CombineArgs {
+  int64_t m, n, ldc;
+  double alpha, beta;
+  double* C;
+  const uint32_t* R;
+  const int32_t* ea;
+  const int32_t* eb;
+};
+
+// Steps 4 and 5: one thread per row i and group of four columns 4w .. 4w+3 (threads of a wave
+// take consecutive rows, so the residue words and C are read in contiguous runs).
+__global__ void __launch_bounds__(256) crt_combine_kernel(CombineArgs a, CrtConst k) {
+  const int64_t words_n = (a.n + 3) / 4;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t w = blockIdx.y;
+  if (i >= a.m) return;
+  uint32_t res[kMaxModuli];
+  for (int l = 0; l < k.nmod; ++l) res[l] = a.R[((int64_t)l * words_n + w) * a.m + i];
+  const int enc_i = a.ea[i];
+#pragma unroll 1
+  for (int c = 0; c < 4; ++c) {
+    const int64_t j = 4 * w + c;
+    if (j >= a.n) break;
+    // S = sum_l r_l W_l, limb by limb in 64 bits (at most 24 * 255 * (2^32 - 1) per limb)
+    uint64_t s[kLimbs] = {0, 0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < k.nmod; ++l) {
+      const uint64_t r = (res[l] >> (8 * c)) & 0xFFu;
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) s[t] += r * k.W[l][t];
+    }
+    uint32_t x[kLimbs];
+    uint64_t carry = 0;
+#pragma unroll
+    for (int t = 0; t < kLimbs; ++t) {
+      const uint64_t v = s[t] + carry;
+      x[t] = (uint32_t)v;
+      carry = v >> 32;
+    }
+    // q ~ S / M (within one of the truth); X = S - q M, then one correction either way.
+    double sf = 0.0;
+#pragma unroll
+    for (int t = kLimbs - 1; t >= 0; --t) sf = sf * 4294967296.0 + (double)x[t];
+    uint64_t q = (uint64_t)floor(sf / k.Mf);
+    uint64_t borrow = 0;
+    {
+      uint64_t mc = 0;
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) {
+        const uint64_t prod = q * k.M[t] + mc;
+        mc = prod >> 32;
+        const uint64_t sub = (uint64_t)(uint32_t)prod + borrow;
+        const uint64_t xv = x[t];
+        x[t] = (uint32_t)(xv - sub);
+        borrow = xv < sub ? 1 : 0;
+      }
+    }
+    auto add_m = [&](uint32_t (&v)[kLimbs]) {
+      uint64_t cy = 0;
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) {
+        const uint64_t u = (uint64_t)v[t] + k.M[t] + cy;
+        v[t] = (uint32_t)u;
+        cy = u >> 32;
+      }
+    };
+    auto ge = [&](const uint32_t (&v)[kLimbs], const uint32_t (&b)[kLimbs]) {
+      for (int t = kLimbs - 1; t >= 0; --t)
+        if (v[t] != b[t]) return v[t] > b[t];
+      return true;
+    };
+    auto sub_from = [&](uint32_t (&v)[kLimbs], const uint32_t (&b)[kLimbs]) {  // v := v - b
+      uint64_t br = 0;
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) {
+        const uint64_t sb = (uint64_t)b[t] + br;
+        br = (uint64_t)v[t] < sb ? 1 : 0;
+        v[t] = (uint32_t)((uint64_t)v[t] - sb);
+      }
+    };
+    if (borrow) add_m(x);               // q was one too large
+    else if (ge(x, k.M)) sub_from(x, k.M);  // q was one too small
+    // Signed representative: X >= M/2 stands for X - M; take its magnitude M - X.
+    bool neg = ge(x, k.half);
+    if (neg) {
+      uint32_t mm[kLimbs];
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) mm[t] = k.M[t];
+      sub_from(mm, x);
+#pragma unroll
+      for (int t = 0; t < kLimbs; ++t) x[t] = mm[t];
+    }
+    // RN(|X|): the top 64 bits, with a sticky bit for anything below, converted once.
+    int top = kLimbs - 1;
+    while (top > 0 && x[top] == 0) --top;
+    double mag;
+    if (top <= 1) {
+      mag = (double)(((uint64_t)x[1] << 32) | x[0]);
+    } else {
+      const int lz = __builtin_clz(x[top]);  // x[top] != 0 here
+      uint64_t hi = ((uint64_t)x[top] << 32) | x[top - 1];
+      uint32_t below = x[top - 2];
+      hi = lz ? (hi << lz) | (below >> (32 - lz)) : hi;
+      below = lz ? below << lz : below;
+      bool sticky = below != 0;
+      for (int t = top - 3; t >= 0; --t) sticky |= x[t] != 0;
+      mag = ldexp((double)(hi | (sticky ? 1u : 0u)), 32 * (top - 1) - lz);
+    }
+    const double xf = neg ? -mag : mag;
+    const int enc_j = a.eb[j];
+    double v;
+    if (enc_i == kNonFinite || enc_j == kNonFinite) {
+      v = __builtin_nan("");
+    } else {
+      v = ldexp(xf, decode_exponent(enc_i) + decode_exponent(enc_j) - 2 * k.bits);
+    }
+    double* cp = a.C + j * a.ldc + i;
+    v = a.alpha * v;
+    *cp = (a.beta != 0.0) ? v + a.beta * *cp : v;
+  }
+}
+
 typedef void (*SliceFn)(const double*, int64_t, int64_t, int64_t, int64_t, int8_t*,
                         const int32_t*);
 typedef void (*GemmFn)(SplitArgs, int, int);
@@ -807,6 +1235,180 @@ int split_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double 
                 dim3(kThreads), s, argv);  // both GEMM kernels run kThreads threads
 }
 
+// ---- Chinese remainder split: host side ----------------------------------------------------------
+
+// Unsigned integers of kLimbs 32-bit limbs (little end first), enough for the modulus products.
+struct Big {
+  uint32_t d[kLimbs] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+Big big_mul_small(const Big& a, uint32_t s) {
+  Big r;
+  uint64_t c = 0;
+  for (int t = 0; t < kLimbs; ++t) {
+    const uint64_t v = (uint64_t)a.d[t] * s + c;
+    r.d[t] = (uint32_t)v;
+    c = v >> 32;
+  }
+  return r;
+}
+
+Big big_div_small(const Big& a, uint32_t s, uint32_t* rem) {
+  Big r;
+  uint64_t c = 0;
+  for (int t = kLimbs - 1; t >= 0; --t) {
+    const uint64_t v = (c << 32) | a.d[t];
+    r.d[t] = (uint32_t)(v / s);
+    c = v % s;
+  }
+  if (rem) *rem = (uint32_t)c;
+  return r;
+}
+
+// a >= (v << sh) for v < 2^64
+bool big_ge_shifted(const Big& a, uint64_t v, int sh) {
+  Big b;
+  const int limb = sh / 32, bit = sh % 32;
+  const unsigned __int128 x = (unsigned __int128)v << bit;
+  for (int t = 0; t < 4; ++t)
+    if (limb + t < kLimbs) b.d[limb + t] = (uint32_t)(x >> (32 * t));
+    else if ((uint32_t)(x >> (32 * t)) != 0) return false;  // beyond the limbs: b > a
+  for (int t = kLimbs - 1; t >= 0; --t)
+    if (a.d[t] != b.d[t]) return a.d[t] > b.d[t];
+  return true;
+}
+
+int inverse_mod(int a, int m) {  // a^-1 mod m for gcd(a, m) = 1
+  int t0 = 0, t1 = 1, r0 = m, r1 = a % m;
+  while (r1) {
+    const int q = r0 / r1;
+    int tmp = r0 - q * r1; r0 = r1; r1 = tmp;
+    tmp = t0 - q * t1; t0 = t1; t1 = tmp;
+  }
+  return t0 < 0 ? t0 + m : t0;
+}
+
+Big crt_modulus_big(int nmod) {
+  Big M;
+  M.d[0] = 1;
+  for (int l = 0; l < nmod; ++l) M = big_mul_small(M, (uint32_t)kModuliHost[l]);
+  return M;
+}
+
+// The largest w <= kCrtMaxBits with 4 k 2^(2w) <= M (0 if none): every |A'B'| < M/2 then.
+int crt_bits_for(int64_t k, int nmod) {
+  if (nmod < 1 || nmod > kMaxModuli || k < 0) return 0;
+  const Big M = crt_modulus_big(nmod);
+  const uint64_t kk = (uint64_t)(k > 1 ? k : 1) * 4u;
+  int w = 0;
+  while (w < kCrtMaxBits && big_ge_shifted(M, kk, 2 * (w + 1))) ++w;
+  return w;
+}
+
+void crt_constants(int nmod, int bits, CrtConst* c) {
+  std::memset(c, 0, sizeof(*c));
+  const Big M = crt_modulus_big(nmod);
+  for (int l = 0; l < nmod; ++l) {
+    uint32_t r = 0;
+    const int m = kModuliHost[l];
+    const Big Ml = big_div_small(M, (uint32_t)m, nullptr);
+    big_div_small(Ml, (uint32_t)m, &r);
+    const Big W = big_mul_small(Ml, (uint32_t)inverse_mod((int)r, m));
+    for (int t = 0; t < kLimbs; ++t) c->W[l][t] = W.d[t];
+  }
+  const Big half = big_div_small(M, 2u, nullptr);
+  double mf = 0.0;
+  for (int t = kLimbs - 1; t >= 0; --t) {
+    c->M[t] = M.d[t];
+    c->half[t] = half.d[t];
+    mf = mf * 4294967296.0 + (double)M.d[t];
+  }
+  c->Mf = mf;
+  c->nmod = nmod;
+  c->bits = bits;
+}
+
+struct CrtLayout {
+  int64_t kp, a_bytes, b_bytes, r_bytes, ea_off, eb_off, r_off, total;
+};
+
+CrtLayout crt_layout(int64_t m, int64_t n, int64_t k, int nmod) {
+  CrtLayout L;
+  L.kp = kpad(k);
+  L.a_bytes = align256((int64_t)nmod * round128(m) * L.kp);
+  L.b_bytes = align256((int64_t)nmod * round128(n) * L.kp);
+  L.r_bytes = align256((int64_t)nmod * m * ((n + 3) / 4) * 4);
+  L.r_off = L.a_bytes + L.b_bytes;
+  L.ea_off = L.r_off + L.r_bytes;
+  L.eb_off = L.ea_off + align256(4 * m);
+  L.total = L.eb_off + align256(4 * n);
+  return L;
+}
+
+// Exponents (pass 1, into zeroed `exps`) and residues of one operand.
+int launch_crt_residues(bool row_contig, const double* X, int64_t ld, int64_t rows, int64_t k,
+                        int64_t kp, int nmod, int bits, int8_t* out, int32_t* exps,
+                        hipStream_t s) {
+  if (rows == 0) return MDG_SUCCESS;
+  if (k > 0) {
+    void* argv[] = {&X, &ld, &rows, &k, &exps};
+    const dim3 grid((unsigned)(round64(rows) / 64), (unsigned)((k + kMaxChunk - 1) / kMaxChunk));
+    const void* fn = row_contig ? reinterpret_cast<const void*>(&split_max_kernel<true>)
+                                : reinterpret_cast<const void*>(&split_max_kernel<false>);
+    const int st = launch(fn, grid, dim3(256), s, argv);
+    if (st) return st;
+  }
+  if (kp == 0) return MDG_SUCCESS;
+  void* argv[] = {&X, &ld, &rows, &k, &kp, &nmod, &bits, &out, &exps};
+  const void* fn = row_contig ? reinterpret_cast<const void*>(&crt_residue_kernel<true>)
+                              : reinterpret_cast<const void*>(&crt_residue_kernel<false>);
+  return launch(fn, dim3((unsigned)(round128(rows) / 64), (unsigned)(kp / 64)), dim3(256), s, argv);
+}
+
+int crt_size_check(int64_t m, int64_t n, int nmod, const CrtLayout& L) {
+  // per-modulus slices are addressed by 32-bit offsets from a 64-bit base
+  if (round128(m) * L.kp > (int64_t)0xFFFFFFFF - 4096 || round128(n) * L.kp > (int64_t)0xFFFFFFFF - 4096)
+    return MDG_ERR_SIZE;
+  const int64_t tiles = ((m + kCrtMT - 1) / kCrtMT) * ((n + kCrtNT - 1) / kCrtNT);
+  if (tiles * nmod > (int64_t)INT32_MAX / 256 || (n + 3) / 4 > 65535 || (m + 255) / 256 > INT32_MAX)
+    return MDG_ERR_SIZE;
+  return MDG_SUCCESS;
+}
+
+int crt_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+            int64_t ldc, int nmod, int8_t* ws, const CrtLayout& L, hipStream_t s) {
+  const int bits = crt_bits_for(k, nmod);
+  int8_t* as = ws;
+  int8_t* bs = ws + L.a_bytes;
+  uint32_t* R = reinterpret_cast<uint32_t*>(ws + L.r_off);
+  int32_t* ea = reinterpret_cast<int32_t*>(ws + L.ea_off);
+  int32_t* eb = reinterpret_cast<int32_t*>(ws + L.eb_off);
+  int st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), ea,
+                       (L.total - L.ea_off) / 4, s);
+  if (st) return st;
+  st = launch_crt_residues(is_trans(transa), A, lda, m, k, L.kp, nmod, bits, as, ea, s);
+  if (st) return st;
+  st = launch_crt_residues(is_notrans(transb), B, ldb, n, k, L.kp, nmod, bits, bs, eb, s);
+  if (st) return st;
+  // INT32 headroom: |a_l b_l| <= 128^2 per term, kCrtKStep terms per step, plus a residue < 256
+  const int fold = (int)(((int64_t)INT32_MAX - 256) / ((int64_t)kCrtKStep * 128 * 128));
+  CrtArgs g{m, n, L.kp, as, bs, R, nmod, fold};
+  int tm = (int)((m + kCrtMT - 1) / kCrtMT), tn = (int)((n + kCrtNT - 1) / kCrtNT);
+  {
+    void* argv[] = {&g, &tm, &tn};
+    st = launch(reinterpret_cast<const void*>(&crt_gemm_kernel),
+                dim3((unsigned)(((int64_t)tm * tn * nmod + 7) / 8 * 8)), dim3(kThreads), s, argv);
+    if (st) return st;
+  }
+  CrtConst kc;
+  crt_constants(nmod, bits, &kc);
+  CombineArgs a{m, n, ldc, alpha, beta, C, R, ea, eb};
+  void* argv[] = {&a, &kc};
+  return launch(reinterpret_cast<const void*>(&crt_combine_kernel),
+                dim3((unsigned)((m + 255) / 256), (unsigned)((n + 3) / 4)), dim3(256), s, argv);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Static scratch for mdg_dgemm_split_noalloc: a file-scope device array, one copy per GPU, held
 // until the process ends. Host code never passes the array's name to a kernel (on the host it is
@@ -923,6 +1525,66 @@ int mdg_dgemm_split_noalloc(char transa, char transb, int64_t m, int64_t n, int6
   if (st) return st;
   return split_run(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nslices, ws, L,
                    static_cast<hipStream_t>(stream));
+}
+
+int mdg_crt_max_moduli(void) { return kMaxModuli; }
+
+int mdg_crt_bits(int64_t k, int nmoduli) { return crt_bits_for(k, nmoduli); }
+
+int64_t mdg_dgemm_crt_workspace_size(int64_t m, int64_t n, int64_t k, int nmoduli) {
+  if (m < 0 || n < 0 || k < 0 || nmoduli < 1 || nmoduli > kMaxModuli) return -1;
+  return crt_layout(m, n, k, nmoduli).total;
+}
+
+int mdg_crt_residues(int operand, char trans, int64_t rows, int64_t k, const double* X, int64_t ld,
+                     int nmoduli, int bits, int8_t* residues, int32_t* exponents, void* stream) {
+  if (operand != 0 && operand != 1) return 1;
+  if (!is_notrans(trans) && !is_trans(trans)) return 2;
+  if (rows < 0) return 3;
+  if (k < 0) return 4;
+  const bool row_contig = operand == 0 ? is_trans(trans) : is_notrans(trans);
+  if (rows > 0 && k > 0 && X == nullptr) return 5;
+  if (ld < max1(row_contig ? k : rows)) return 6;
+  if (nmoduli < 1 || nmoduli > kMaxModuli) return 7;
+  if (bits < 1 || bits > kCrtMaxBits) return 8;
+  if (rows > 0 && (residues == nullptr || exponents == nullptr)) return 9;
+  if (rows == 0) return MDG_SUCCESS;
+  int st = mdg_device_check();
+  if (st) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = launch_fill(reinterpret_cast<const void*>(&zero_i32_kernel), exponents, rows, s);
+  if (st) return st;
+  st = launch_crt_residues(row_contig, X, ld, rows, k, kpad(k), nmoduli, bits, residues, exponents,
+                           s);
+  if (st) return st;
+  return launch_fill(reinterpret_cast<const void*>(&decode_exponents_kernel), exponents, rows, s);
+}
+
+int mdg_dgemm_crt(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                  double* C, int64_t ldc, int nmoduli, void* workspace, int64_t workspace_bytes,
+                  void* stream) {
+  if (nmoduli < 1 || nmoduli > kMaxModuli) {
+    // report an earlier bad argument first, as for the other entry points
+    const int st = split_check(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 1);
+    return st ? st : 14;
+  }
+  int st = split_check(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 1);
+  if (st) return st;
+  const bool no_product = (alpha == 0.0 || k == 0);
+  if (m == 0 || n == 0 || (no_product && beta == 1.0)) return MDG_SUCCESS;
+  if (no_product)  // C := beta*C needs no residues: the native entry point does exactly this
+    return mdg_dgemm(transa, transb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+  if (crt_bits_for(k, nmoduli) < 1) return 14;  // too few moduli for this k
+  const CrtLayout L = crt_layout(m, n, k, nmoduli);
+  if (workspace == nullptr || workspace_bytes < L.total) return 15;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return 15;
+  st = crt_size_check(m, n, nmoduli, L);
+  if (st) return st;
+  st = mdg_device_check();
+  if (st) return st;
+  return crt_run(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nmoduli,
+                 static_cast<int8_t*>(workspace), L, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -292,3 +292,26 @@ def test_split_entry_points_check_the_device_after_the_arguments():
     st = mdg.mdg_split_slices(0, "N", 64, 64, fake, 64, 7, fake, fake)
     assert st in (mdg.MDG_ERR_HIP, mdg.MDG_ERR_DEVICE)
     assert mdg.mdg_split_slices(0, "N", 64, 64, fake, 63, 7, fake, fake) == 6
+
+
+def test_crt_bits_and_workspace_are_host_logic():
+    import oracle.ozaki as oz
+    for nmod in range(1, mdg.mdg_crt_max_moduli() + 1):
+        for k in (0, 1, 7, 32, 1000, 8192, 140000):
+            assert mdg.mdg_crt_bits(k, nmod) == oz.crt_bits(k, nmod), (k, nmod)
+    assert mdg.mdg_crt_bits(100, 0) == 0 and mdg.mdg_crt_bits(100, 25) == 0
+    assert tuple(oz.MODULI) == (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199,
+                                197, 193, 191, 181, 179, 173, 167, 163, 157, 151, 149)
+    rnd = lambda x, a: -(-x // a) * a  # noqa: E731
+    m, n, k, N = 300, 190, 70, 15
+    want = (rnd(N * 384 * 128, 256) + rnd(N * 256 * 128, 256) + rnd(N * m * rnd(n, 4), 256)
+            + rnd(4 * m, 256) + rnd(4 * n, 256))
+    assert mdg.mdg_dgemm_crt_workspace_size(m, n, k, N) == want
+    assert mdg.mdg_dgemm_crt_workspace_size(m, n, k, 0) == -1
+    fake = 1 << 40
+    st = mdg.mdg_dgemm_crt("N", "N", 64, 64, 64, 1.0, fake, 64, fake, 64, 0.0, fake, 64, 15, fake,
+                           mdg.mdg_dgemm_crt_workspace_size(64, 64, 64, 15))
+    assert st in (mdg.MDG_ERR_HIP, mdg.MDG_ERR_DEVICE)
+    assert mdg.mdg_dgemm_crt("N", "N", 64, 64, 64, 1.0, fake, 63, fake, 64, 0.0, fake, 64, 0,
+                             fake, 0) == 8   # an earlier bad argument is reported first
+    assert mdg.mdg_crt_residues(0, "N", 64, 64, fake, 64, 15, 73, fake, fake) == 8

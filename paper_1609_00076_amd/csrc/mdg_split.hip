@@ -690,11 +690,14 @@ __device__ __forceinline__ int mod_small(int v, int m, float inv) {
   return r;
 }
 
-// Residues of 16 scaled entries (already integers of at most 72 bits held in binary64) for one
-// modulus, as 16 int8 bytes in the symmetric range. Each |a| splits exactly into three 24-bit
-// parts, a = a2 2^48 + a1 2^24 + a0, reduced separately.
+// Residues of 16 scaled entries (integers of at most 72 bits held in binary64) for one modulus,
+// as 16 int8 bytes in the symmetric range. |a| = c 2^t with c < 2^53 an integer (t > 0 only past
+// 53 bits, where the low bits of a are zero), so |a| mod m = (c mod m)(2^t mod m) mod m; c mod m is
+// c - q m with q = floor(c / m) from the binary64 quotient, which is within one of the truth, and
+// the remainder c - q m is exact (one fused multiply-add of a result below 2m in magnitude).
 struct Parts16 {
-  int p0[16], p1[16], p2[16];
+  double c[16];
+  int t[16];
   bool neg[16];
 };
 
@@ -702,30 +705,34 @@ __device__ __forceinline__ void split_parts(const double (&a)[16], Parts16& q) {
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const double x = fabs(a[e]);
-    const double h2 = floor(ldexp(x, -48));
-    const double rem = x - ldexp(h2, 48);
-    const double h1 = floor(ldexp(rem, -24));
-    q.p2[e] = (int)h2;
-    q.p1[e] = (int)h1;
-    q.p0[e] = (int)(rem - ldexp(h1, 24));
+    int ex = 0;
+    (void)frexp(x, &ex);  // x < 2^ex
+    const int t = ex > 53 ? ex - 53 : 0;
+    q.c[e] = ldexp(x, -t);
+    q.t[e] = t;
     q.neg[e] = a[e] < 0.0;
   }
 }
 
 __device__ __forceinline__ v4i residues16(const Parts16& q, int m) {
-  const float inv = 1.0f / (float)m;
-  const int c24 = mod_small(1 << 23, m, inv) * 2 % m;  // 2^24 mod m
-  const int c48 = mod_small(c24 * c24, m, inv);         // 2^48 mod m
+  const double dm = (double)m, inv = 1.0 / dm;
+  const float finv = 1.0f / (float)m;
   const int half = m - m / 2;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    int r = mod_small(mod_small(q.p2[e], m, inv) * c48 + mod_small(q.p1[e], m, inv) * c24 +
-                          mod_small(q.p0[e], m, inv),
-                      m, inv);
-    if (q.neg[e] && r != 0) r = m - r;
-    if (r >= half) r -= m;
-    w[e / 4] |= ((uint32_t)r & 0xFFu) << (8 * (e % 4));
+    const double c = q.c[e];
+    double r = fma(-floor(c * inv), dm, c);
+    r += (r < 0.0) ? dm : 0.0;
+    r -= (r >= dm) ? dm : 0.0;
+    int x = (int)r;
+    if (q.t[e]) {  // times 2^t mod m, t < 20: (2^t mod m) by one shift and reduction
+      const int p2 = mod_small(1 << q.t[e], m, finv);
+      x = mod_small(x * p2, m, finv);
+    }
+    if (q.neg[e] && x != 0) x = m - x;
+    if (x >= half) x -= m;
+    w[e / 4] |= ((uint32_t)x & 0xFFu) << (8 * (e % 4));
   }
   return (v4i){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
 }
@@ -955,12 +962,15 @@ crt_gemm_kernel(CrtArgs g, int tiles_m, int tiles_n) {
   crt_gemm_tile(g, tiles_m, tiles_n, lds);
 }
 
-// Step 4 and 5 constants, computed on the host for the call's modulus count.
+// Step 4 and 5 constants, computed on the host for the call's modulus count. Step 4 works in
+// 16-bit limbs (little end first), so that a residue times a limb fits 24 bits and a sum over all
+// moduli fits 32.
+constexpr int kLimbs16 = 2 * kLimbs;
 struct CrtConst {
-  uint32_t W[kMaxModuli][kLimbs];  // W_l
-  uint32_t M[kLimbs];
-  uint32_t half[kLimbs];           // M / 2
-  double Mf;                       // M rounded to binary64
+  uint16_t W[kMaxModuli][kLimbs16];  // W_l
+  uint16_t M[kLimbs16];
+  uint32_t half[kLimbs];             // M / 2, 32-bit limbs
+  double Mf;                         // M rounded to binary64
   int nmod, bits;
 };
 
@@ -974,8 +984,11 @@ struct CombineArgs {
 };
 
 // Steps 4 and 5: one thread per row i and group of four columns 4w .. 4w+3 (threads of a wave
-// take consecutive rows, so the residue words and C are read in contiguous runs).
+// take consecutive rows, so the residue words and C are read in contiguous runs). L32: 32-bit
+// limbs enough for sum_l r_l W_l (the host picks the smallest).
+template <int L32>
 __global__ void __launch_bounds__(256) crt_combine_kernel(CombineArgs a, CrtConst k) {
+  constexpr int L = 2 * L32;  // 16-bit limbs
   const int64_t words_n = (a.n + 3) / 4;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t w = blockIdx.y;
@@ -987,80 +1000,83 @@ __global__ void __launch_bounds__(256) crt_combine_kernel(CombineArgs a, CrtCons
   for (int c = 0; c < 4; ++c) {
     const int64_t j = 4 * w + c;
     if (j >= a.n) break;
-    // S = sum_l r_l W_l, limb by limb in 64 bits (at most 24 * 255 * (2^32 - 1) per limb)
-    uint64_t s[kLimbs] = {0, 0, 0, 0, 0, 0, 0};
+    // S = sum_l r_l W_l: 24-bit products, at most 24 of them per limb
+    uint32_t s[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) s[t] = 0;
     for (int l = 0; l < k.nmod; ++l) {
-      const uint64_t r = (res[l] >> (8 * c)) & 0xFFu;
+      const uint32_t r = (res[l] >> (8 * c)) & 0xFFu;
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) s[t] += r * k.W[l][t];
+      for (int t = 0; t < L; ++t) s[t] += __umul24(r, (uint32_t)k.W[l][t]);
     }
-    uint32_t x[kLimbs];
-    uint64_t carry = 0;
+    uint32_t carry = 0;
 #pragma unroll
-    for (int t = 0; t < kLimbs; ++t) {
-      const uint64_t v = s[t] + carry;
-      x[t] = (uint32_t)v;
-      carry = v >> 32;
+    for (int t = 0; t < L; ++t) {
+      const uint32_t v = s[t] + carry;
+      s[t] = v & 0xFFFFu;
+      carry = v >> 16;
     }
     // q ~ S / M (within one of the truth); X = S - q M, then one correction either way.
     double sf = 0.0;
 #pragma unroll
-    for (int t = kLimbs - 1; t >= 0; --t) sf = sf * 4294967296.0 + (double)x[t];
-    uint64_t q = (uint64_t)floor(sf / k.Mf);
-    uint64_t borrow = 0;
-    {
-      uint64_t mc = 0;
+    for (int t = L - 1; t >= 0; --t) sf = sf * 65536.0 + (double)s[t];
+    const uint32_t q = (uint32_t)floor(sf / k.Mf);
+    uint32_t mc = 0, borrow = 0;
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) {
-        const uint64_t prod = q * k.M[t] + mc;
-        mc = prod >> 32;
-        const uint64_t sub = (uint64_t)(uint32_t)prod + borrow;
-        const uint64_t xv = x[t];
-        x[t] = (uint32_t)(xv - sub);
-        borrow = xv < sub ? 1 : 0;
-      }
+    for (int t = 0; t < L; ++t) {
+      const uint32_t prod = q * (uint32_t)k.M[t] + mc;  // < 2^13 * 2^16 + 2^13
+      mc = prod >> 16;
+      const uint32_t sub = (prod & 0xFFFFu) + borrow;
+      borrow = s[t] < sub ? 1u : 0u;
+      s[t] = (s[t] + (borrow << 16) - sub) & 0xFFFFu;
     }
-    auto add_m = [&](uint32_t (&v)[kLimbs]) {
+    uint32_t x[L32];
+#pragma unroll
+    for (int t = 0; t < L32; ++t) x[t] = s[2 * t] | (s[2 * t + 1] << 16);
+    uint32_t M32[L32];
+#pragma unroll
+    for (int t = 0; t < L32; ++t) M32[t] = (uint32_t)k.M[2 * t] | ((uint32_t)k.M[2 * t + 1] << 16);
+    auto ge = [&](const uint32_t (&v)[L32], const uint32_t* b) {
+      for (int t = L32 - 1; t >= 0; --t)
+        if (v[t] != b[t]) return v[t] > b[t];
+      return true;
+    };
+    auto add_to = [&](uint32_t (&v)[L32], const uint32_t* b) {  // v := v + b (mod 2^(32 L32))
       uint64_t cy = 0;
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) {
-        const uint64_t u = (uint64_t)v[t] + k.M[t] + cy;
+      for (int t = 0; t < L32; ++t) {
+        const uint64_t u = (uint64_t)v[t] + b[t] + cy;
         v[t] = (uint32_t)u;
         cy = u >> 32;
       }
     };
-    auto ge = [&](const uint32_t (&v)[kLimbs], const uint32_t (&b)[kLimbs]) {
-      for (int t = kLimbs - 1; t >= 0; --t)
-        if (v[t] != b[t]) return v[t] > b[t];
-      return true;
-    };
-    auto sub_from = [&](uint32_t (&v)[kLimbs], const uint32_t (&b)[kLimbs]) {  // v := v - b
+    auto sub_from = [&](uint32_t (&v)[L32], const uint32_t* b) {  // v := v - b
       uint64_t br = 0;
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) {
+      for (int t = 0; t < L32; ++t) {
         const uint64_t sb = (uint64_t)b[t] + br;
         br = (uint64_t)v[t] < sb ? 1 : 0;
         v[t] = (uint32_t)((uint64_t)v[t] - sb);
       }
     };
-    if (borrow) add_m(x);               // q was one too large
-    else if (ge(x, k.M)) sub_from(x, k.M);  // q was one too small
+    if (borrow) add_to(x, M32);              // q was one too large
+    else if (ge(x, M32)) sub_from(x, M32);   // q was one too small
     // Signed representative: X >= M/2 stands for X - M; take its magnitude M - X.
-    bool neg = ge(x, k.half);
+    const bool neg = ge(x, k.half);
     if (neg) {
-      uint32_t mm[kLimbs];
+      uint32_t mm[L32];
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) mm[t] = k.M[t];
+      for (int t = 0; t < L32; ++t) mm[t] = M32[t];
       sub_from(mm, x);
 #pragma unroll
-      for (int t = 0; t < kLimbs; ++t) x[t] = mm[t];
+      for (int t = 0; t < L32; ++t) x[t] = mm[t];
     }
     // RN(|X|): the top 64 bits, with a sticky bit for anything below, converted once.
-    int top = kLimbs - 1;
+    int top = L32 - 1;
     while (top > 0 && x[top] == 0) --top;
     double mag;
     if (top <= 1) {
-      mag = (double)(((uint64_t)x[1] << 32) | x[0]);
+      mag = (double)(((uint64_t)(L32 > 1 ? x[1] : 0u) << 32) | x[0]);
     } else {
       const int lz = __builtin_clz(x[top]);  // x[top] != 0 here
       uint64_t hi = ((uint64_t)x[top] << 32) | x[top - 1];
@@ -1305,7 +1321,9 @@ int crt_bits_for(int64_t k, int nmod) {
   return w;
 }
 
-void crt_constants(int nmod, int bits, CrtConst* c) {
+// Fills the step 4 constants; returns the number of 32-bit limbs sum_l r_l W_l needs (below
+// nmod * 256 * M).
+int crt_constants(int nmod, int bits, CrtConst* c) {
   std::memset(c, 0, sizeof(*c));
   const Big M = crt_modulus_big(nmod);
   for (int l = 0; l < nmod; ++l) {
@@ -1314,18 +1332,26 @@ void crt_constants(int nmod, int bits, CrtConst* c) {
     const Big Ml = big_div_small(M, (uint32_t)m, nullptr);
     big_div_small(Ml, (uint32_t)m, &r);
     const Big W = big_mul_small(Ml, (uint32_t)inverse_mod((int)r, m));
-    for (int t = 0; t < kLimbs; ++t) c->W[l][t] = W.d[t];
+    for (int t = 0; t < kLimbs; ++t) {
+      c->W[l][2 * t] = (uint16_t)(W.d[t] & 0xFFFFu);
+      c->W[l][2 * t + 1] = (uint16_t)(W.d[t] >> 16);
+    }
   }
   const Big half = big_div_small(M, 2u, nullptr);
   double mf = 0.0;
   for (int t = kLimbs - 1; t >= 0; --t) {
-    c->M[t] = M.d[t];
+    c->M[2 * t] = (uint16_t)(M.d[t] & 0xFFFFu);
+    c->M[2 * t + 1] = (uint16_t)(M.d[t] >> 16);
     c->half[t] = half.d[t];
     mf = mf * 4294967296.0 + (double)M.d[t];
   }
   c->Mf = mf;
   c->nmod = nmod;
   c->bits = bits;
+  const Big bound = big_mul_small(M, (uint32_t)nmod * 256u);
+  int limbs = kLimbs;
+  while (limbs > 1 && bound.d[limbs - 1] == 0) --limbs;
+  return limbs;
 }
 
 struct CrtLayout {
@@ -1402,11 +1428,15 @@ int crt_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double al
     if (st) return st;
   }
   CrtConst kc;
-  crt_constants(nmod, bits, &kc);
+  const int limbs = crt_constants(nmod, bits, &kc);
   CombineArgs a{m, n, ldc, alpha, beta, C, R, ea, eb};
   void* argv[] = {&a, &kc};
-  return launch(reinterpret_cast<const void*>(&crt_combine_kernel),
-                dim3((unsigned)((m + 255) / 256), (unsigned)((n + 3) / 4)), dim3(256), s, argv);
+  const void* fn = limbs <= 3   ? reinterpret_cast<const void*>(&crt_combine_kernel<3>)
+                   : limbs == 4 ? reinterpret_cast<const void*>(&crt_combine_kernel<4>)
+                   : limbs == 5 ? reinterpret_cast<const void*>(&crt_combine_kernel<5>)
+                   : limbs == 6 ? reinterpret_cast<const void*>(&crt_combine_kernel<6>)
+                                : reinterpret_cast<const void*>(&crt_combine_kernel<7>);
+  return launch(fn, dim3((unsigned)((m + 255) / 256), (unsigned)((n + 3) / 4)), dim3(256), s, argv);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -785,11 +785,19 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* X, int64
 // modulo m_l and writes them, four columns to a 32-bit word, to R_l[(j/4) m + i] (R_l holds
 // m * ceil(n/4) words). Workgroups are ordered modulus-major, so each XCD works on one or two
 // moduli at a time and their residue slices stay in its L2 and the Infinity Cache.
-constexpr int kCrtMT = 256, kCrtNT = 128, kCrtKStep = 32, kCrtStages = 3;
-constexpr int kCrtACh = kCrtMT / 32, kCrtBCh = kCrtNT / 32, kCrtCh = kCrtACh + kCrtBCh;
-constexpr int kCrtLoads = (kCrtCh + 7) / 8;         // direct loads per wave per stage
-constexpr int kCrtStage = kCrtCh * kChunk;
-constexpr int kCrtLds = kCrtStages * kCrtStage + kChunk;  // + a trash chunk for idle loads
+constexpr int kCrtMT = 256, kCrtNT = 128, kCrtStages = 3;
+constexpr int kCrtACh = kCrtMT / 32, kCrtBCh = kCrtNT / 32;
+// KH: 32-deep k-panels per stage (a stage holds KH panels of A's 8 chunks and B's 4).
+template <int KH>
+struct CrtCfg {
+  static constexpr int KSTEP = 32 * KH;
+  static constexpr int CH = KH * (kCrtACh + kCrtBCh);  // chunks per stage
+  static constexpr int LOADS = (CH + 7) / 8;           // direct loads per wave per stage
+  static constexpr int STAGE = CH * kChunk;
+  static constexpr int LDS = kCrtStages * STAGE + kChunk;  // + a trash chunk for idle loads
+  static_assert((kCrtStages - 1) * LOADS <= 63, "vmcnt range");
+};
+constexpr int kCrtKH = 2;  // the configuration the library runs
 
 struct CrtArgs {
   int64_t m, n, kp;
@@ -800,8 +808,10 @@ struct CrtArgs {
   int fold_steps;    // k-steps after which the accumulators are reduced modulo m_l
 };
 
+template <int KH>
 __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int tiles_n,
                                               int8_t* lds) {
+  using K = CrtCfg<KH>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave_m = wave & 3, wave_n = wave >> 2;
@@ -828,46 +838,52 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   const int64_t slice_a = rpa * g.kp, slice_b = rpb * g.kp;
   const int8_t* a_base = g.As + l * slice_a;
   const int8_t* b_base = g.Bs + l * slice_b;
-  const int nsteps = (int)(g.kp / kCrtKStep);  // >= 2: kp is a positive multiple of 64
+  const int nsteps = (int)(g.kp / K::KSTEP);  // >= 1: kp is a positive multiple of 64
 
-  // Direct load u of wave w moves chunk c = 8u + w: c < 8 is rows 32c.. of A, c < 12 rows
-  // 32(c - 8).. of B, the rest idle (an empty buffer into the trash chunk).
-  uint32_t voff[kCrtLoads];
+  // Direct load u of wave w moves chunk c = 8u + w of the stage: chunk c < 8 KH is rows
+  // 32 (c % 8).. of A in panel c / 8 of the step, c < 12 KH rows 32 (c' % 4).. of B in panel
+  // c' / 4 (c' = c - 8 KH), the rest idle (an empty buffer into the trash chunk).
+  uint32_t voff[K::LOADS];
 #pragma unroll
-  for (int u = 0; u < kCrtLoads; ++u) {
+  for (int u = 0; u < K::LOADS; ++u) {
     const int c = 8 * u + wave;
     int64_t o = 0;
-    if (c < kCrtACh) o = (row0 + 32 * c) * kCrtKStep;
-    else if (c < kCrtCh) o = (col0 + 32 * (c - kCrtACh)) * kCrtKStep;
+    if (c < kCrtACh * KH) o = (c / kCrtACh) * rpa * 32 + (row0 + 32 * (c % kCrtACh)) * 32;
+    else if (c < K::CH) {
+      const int cb = c - kCrtACh * KH;
+      o = (cb / kCrtBCh) * rpb * 32 + (col0 + 32 * (cb % kCrtBCh)) * 32;
+    }
     voff[u] = (uint32_t)o + 16u * (uint32_t)lane;
   }
   auto issue = [&](int ks) __attribute__((always_inline)) {
-    int8_t* st = lds + (ks % kCrtStages) * kCrtStage;
+    int8_t* st = lds + (ks % kCrtStages) * K::STAGE;
 #pragma unroll
-    for (int u = 0; u < kCrtLoads; ++u) {
+    for (int u = 0; u < K::LOADS; ++u) {
       const int c = 8 * u + wave;
-      const bool is_a = c < kCrtACh, is_b = !is_a && c < kCrtCh;
+      const bool is_a = c < kCrtACh * KH, is_b = !is_a && c < K::CH;
       const int8_t* base = is_b ? b_base : a_base;
       const int64_t bytes = is_a ? slice_a : is_b ? slice_b : 0;
-      const uint32_t soff = is_a ? (uint32_t)ks * (uint32_t)(rpa * kCrtKStep)
-                                 : is_b ? (uint32_t)ks * (uint32_t)(rpb * kCrtKStep) : 0u;
-      int8_t* dst = (is_a || is_b) ? st + c * kChunk : lds + kCrtStages * kCrtStage;
+      const uint32_t soff = is_a ? (uint32_t)ks * (uint32_t)(rpa * K::KSTEP)
+                                 : is_b ? (uint32_t)ks * (uint32_t)(rpb * K::KSTEP) : 0u;
+      int8_t* dst = (is_a || is_b) ? st + c * kChunk : lds + kCrtStages * K::STAGE;
       __builtin_amdgcn_raw_ptr_buffer_load_lds(make_rsrc(base, bytes), (lds_void_ptr)dst, 16,
                                                voff[u], (int)soff, 0, 0);
     }
   };
 
   const int frag = 16 * row_slot(lane & 31, lane >> 5);
-  const int a_frag = 2 * wave_m * kChunk + frag;               // + bi KiB
-  const int b_frag = (kCrtACh + 2 * wave_n) * kChunk + frag;   // + bj KiB
-  v4i af[2], bf[2];
+  const int a_frag = 2 * wave_m * kChunk + frag;                    // + (bi + 8 h) KiB
+  const int b_frag = (kCrtACh * KH + 2 * wave_n) * kChunk + frag;   // + (bj + 4 h) KiB
+  v4i af[KH][2], bf[KH][2];
   auto read = [&](int ks) __attribute__((always_inline)) {
-    const int8_t* st = lds + (ks % kCrtStages) * kCrtStage;
+    const int8_t* st = lds + (ks % kCrtStages) * K::STAGE;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      af[b] = *reinterpret_cast<const v4i*>(st + a_frag + b * kChunk);
-      bf[b] = *reinterpret_cast<const v4i*>(st + b_frag + b * kChunk);
-    }
+    for (int h = 0; h < KH; ++h)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        af[h][b] = *reinterpret_cast<const v4i*>(st + a_frag + (b + kCrtACh * h) * kChunk);
+        bf[h][b] = *reinterpret_cast<const v4i*>(st + b_frag + (b + kCrtBCh * h) * kChunk);
+      }
   };
 
   v16i acc[2][2];
@@ -897,18 +913,25 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
           acc[bi][bj][r] = x;
         }
   };
+  // The step's MFMAs, kept ahead of the wait and barrier that follow them (sched_barrier), so
+  // the matrix unit works through them while the wave waits.
   auto mfma = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int h = 0; h < KH; ++h)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[bj], af[bi], acc[bi][bj], 0, 0, 0);
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[h][bj], af[h][bi], acc[bi][bj],
+                                                              0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   };
 
   const int pre = nsteps < kCrtStages ? nsteps : kCrtStages;
   for (int ks = 0; ks < pre; ++ks) issue(ks);
-  if (pre == 3) wait_vm_lgkm0<2 * kCrtLoads>();
-  else wait_vm_lgkm0<kCrtLoads>();  // two steps issued, the first has landed
+  if (pre == 3) wait_vm_lgkm0<2 * K::LOADS>();
+  else if (pre == 2) wait_vm_lgkm0<K::LOADS>();
+  else wait_vm_lgkm0<0>();
   bare_barrier();
   read(0);
   // Steady state: the fragments of step ks are in registers. Multiply, wait for step ks + 1's
@@ -916,7 +939,7 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   int ks = 0, since_fold = 0;
   for (; ks + 3 < nsteps; ++ks) {
     mfma();
-    wait_vm_lgkm0<kCrtLoads>();
+    wait_vm_lgkm0<K::LOADS>();
     bare_barrier();
     issue(ks + 3);
     read(ks + 1);
@@ -927,7 +950,7 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   }
   for (; ks + 1 < nsteps; ++ks) {  // drain: no loads left to issue
     mfma();
-    if (ks + 2 < nsteps) wait_vm_lgkm0<kCrtLoads>();
+    if (ks + 2 < nsteps) wait_vm_lgkm0<K::LOADS>();
     else wait_vm_lgkm0<0>();
     bare_barrier();
     read(ks + 1);
@@ -956,10 +979,11 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   }
 }
 
+template <int KH>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 crt_gemm_kernel(CrtArgs g, int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(1024))) int8_t lds[kCrtLds];
-  crt_gemm_tile(g, tiles_m, tiles_n, lds);
+  __shared__ __attribute__((aligned(1024))) int8_t lds[CrtCfg<KH>::LDS];
+  crt_gemm_tile<KH>(g, tiles_m, tiles_n, lds);
 }
 
 // Step 4 and 5 constants, computed on the host for the call's modulus count. Step 4 works in
@@ -1417,13 +1441,13 @@ int crt_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double al
   if (st) return st;
   st = launch_crt_residues(is_notrans(transb), B, ldb, n, k, L.kp, nmod, bits, bs, eb, s);
   if (st) return st;
-  // INT32 headroom: |a_l b_l| <= 128^2 per term, kCrtKStep terms per step, plus a residue < 256
-  const int fold = (int)(((int64_t)INT32_MAX - 256) / ((int64_t)kCrtKStep * 128 * 128));
+  // INT32 headroom: |a_l b_l| <= 128^2 per term, KSTEP terms per step, plus a residue < 256
+  const int fold = (int)(((int64_t)INT32_MAX - 256) / ((int64_t)CrtCfg<kCrtKH>::KSTEP * 128 * 128));
   CrtArgs g{m, n, L.kp, as, bs, R, nmod, fold};
   int tm = (int)((m + kCrtMT - 1) / kCrtMT), tn = (int)((n + kCrtNT - 1) / kCrtNT);
   {
     void* argv[] = {&g, &tm, &tn};
-    st = launch(reinterpret_cast<const void*>(&crt_gemm_kernel),
+    st = launch(reinterpret_cast<const void*>(&crt_gemm_kernel<kCrtKH>),
                 dim3((unsigned)(((int64_t)tm * tn * nmod + 7) / 8 * 8)), dim3(kThreads), s, argv);
     if (st) return st;
   }

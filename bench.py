@@ -229,7 +229,9 @@ def max_rel_err(got, ref, D):
         return float("inf")
     return float(np.max(np.where(zero, 0.0, diff / np.where(zero, 1.0, D)))) if diff.size else 0.0
 
-SPLIT_CASES = [(0, 7), (8, 8), (32, 10)]  # (phi, nslices) that reach err <= 1e-13
+# (phi, nslices, nmoduli) that reach err <= 1e-13 at 8192^3: slice counts for the slice scheme,
+# modulus counts for the Chinese-remainder scheme
+SPLIT_CASES = [(0, 7, 14), (8, 8, 15), (32, 10, 16)]
 INT8_PEAK_TOPS = 5000.0
 
 
@@ -249,36 +251,44 @@ def events_ms(torch, fn, reps, warmup):
 
 
 def split_result(args, torch, mdg):
-    """Workload 3: split-precision dgemm (INT8 MFMA slices) against the native FP64 kernel, NN
-    8192^3, phi in {0, 8, 32}. Times the whole split call, the two slicing steps alone (so the
-    slice-product GEMM kernel's time is the difference) and the native call; in the CPU-baseline
-    leg the oracle computes sampled full rows and columns, which are timed and also give the split
-    and native results' errors (and a doubled-precision sample gives the true error)."""
+    """Workload 3: split-precision dgemm on the INT8 matrix cores against the native FP64 kernel,
+    NN 8192^3, phi in {0, 8, 32}, by both schemes: slices (Ozaki scheme I, S(S+1)/2 slice products)
+    and the Chinese remainder theorem (scheme II, one product per modulus). Times each whole call,
+    its operand-splitting steps alone, and the native call; in the CPU-baseline leg the oracle
+    computes sampled full rows and columns, which are timed and also give every result's error
+    (and a doubled-precision sample gives the true error)."""
     import numpy as np
 
     import synth
     m = n = k = args.split_size
     cases, cpu_parts = [], []
     cpu_flops = cpu_s = 0.0
-    for phi, S in SPLIT_CASES:
+    fl = 2.0 * m * n * k
+    for phi, S, N in SPLIT_CASES:
         dist = "scaled" if phi else "uniform"
         p = synth.problem(3, phi, "N", "N", m, n, k, ld_rule=synth.ld_round8, dist=dist, phi=phi)
         lda, ldb, ldc = p["lda"], p["ldb"], p["ldc"]
         dA, dB, dC0 = (torch.from_numpy(p[x]).cuda() for x in "ABC")
-        ws_bytes = mdg.mdg_dgemm_split_workspace_size(m, n, k, S)
-        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         dC = dC0.clone()
+        ws_s = mdg.mdg_dgemm_split_workspace_size(m, n, k, S)
+        ws_c = mdg.mdg_dgemm_crt_workspace_size(m, n, k, N)
+        ws = torch.empty(max(ws_s, ws_c), dtype=torch.uint8, device="cuda")
         rp, kp = (m + 127) // 128 * 128, (k + 63) // 64 * 64
-        sl = torch.empty(S * rp * kp, dtype=torch.int8, device="cuda")
+        sl = torch.empty(max(S, N) * rp * kp, dtype=torch.int8, device="cuda")
         ex = torch.empty(max(m, n), dtype=torch.int32, device="cuda")
+        bits = mdg.mdg_crt_bits(k, N)
 
         def check(st):
             if st:
                 raise RuntimeError(mdg.mdg_status_string(st))
 
-        def split_call():
+        def slices_call():
             check(mdg.mdg_dgemm_split("N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 1.0, dC, ldc, S, ws,
-                                      ws_bytes))
+                                      ws_s))
+
+        def crt_call():
+            check(mdg.mdg_dgemm_crt("N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 1.0, dC, ldc, N, ws,
+                                    ws_c))
 
         def native_call():
             check(mdg.mdg_dgemm("N", "N", m, n, k, 1.0, dA, lda, dB, ldb, 1.0, dC, ldc))
@@ -287,37 +297,46 @@ def split_result(args, torch, mdg):
             check(mdg.mdg_split_slices(0, "N", m, k, dA, lda, S, sl, ex))
             check(mdg.mdg_split_slices(1, "N", n, k, dB, ldb, S, sl, ex))
 
-        split_ms = events_ms(torch, split_call, args.steps, args.warmup)
-        native_ms = events_ms(torch, native_call, args.steps, args.warmup)
-        slice_ms = events_ms(torch, slicing_only, args.steps, args.warmup)
-        gemm_ms = split_ms - slice_ms
+        def residues_only():
+            check(mdg.mdg_crt_residues(0, "N", m, k, dA, lda, N, bits, sl, ex))
+            check(mdg.mdg_crt_residues(1, "N", n, k, dB, ldb, N, bits, sl, ex))
+
+        t = {name: events_ms(torch, fn, args.steps, args.warmup)
+             for name, fn in (("slices", slices_call), ("crt", crt_call), ("native", native_call),
+                              ("slicing", slicing_only), ("residues", residues_only))}
         # one result of each path from the original C, for the error figures
-        dC.copy_(dC0)
-        split_call()
-        c_split = dC.view(n, ldc)[:, :m].T.cpu().numpy()
-        dC.copy_(dC0)
-        native_call()
-        c_native = dC.view(n, ldc)[:, :m].T.cpu().numpy()
+        outs = {}
+        for name, fn in (("slices", slices_call), ("crt", crt_call), ("native", native_call)):
+            dC.copy_(dC0)
+            fn()
+            outs[name] = dC.view(n, ldc)[:, :m].T.cpu().numpy()
         del dA, dB, dC, dC0, ws, sl, ex
         torch.cuda.empty_cache()
-        fl = 2.0 * m * n * k
-        products = S * (S + 1) // 2
+        sp = S * (S + 1) // 2
         case = {
-            "phi": phi, "nslices": S, "slice_products": products,
-            "split_ms": round(split_ms, 3), "native_ms": round(native_ms, 3),
-            "slicing_ms": round(slice_ms, 3), "gemm_kernel_ms": round(gemm_ms, 3),
-            "split_tflops_equiv": round(fl / (split_ms * 1e-3) / 1e12, 2),
-            "native_tflops": round(fl / (native_ms * 1e-3) / 1e12, 2),
-            "speedup_vs_native": round(native_ms / split_ms, 3),
-            "int8_tops_gemm_kernel": round(products * fl / (gemm_ms * 1e-3) / 1e12, 1),
-            "int8_frac_gemm_kernel": round(products * fl / (gemm_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS,
-                                           4),
-            "max_err_vs_oracle": None, "native_max_err_vs_oracle": None,
-            "true_err_vs_doubled_precision": None,
+            "phi": phi, "native_ms": round(t["native"], 3),
+            "native_tflops": round(fl / (t["native"] * 1e-3) / 1e12, 2),
+            "crt": {"nmoduli": N, "bits": bits, "int8_products": N, "ms": round(t["crt"], 3),
+                    "residues_ms": round(t["residues"], 3),
+                    "products_and_recombination_ms": round(t["crt"] - t["residues"], 3),
+                    "tflops_equiv": round(fl / (t["crt"] * 1e-3) / 1e12, 2),
+                    "speedup_vs_native": round(t["native"] / t["crt"], 3),
+                    "int8_tops_excl_residues": round(N * fl / ((t["crt"] - t["residues"]) * 1e-3)
+                                                     / 1e12, 1),
+                    "max_err_vs_oracle": None, "true_err_vs_doubled_precision": None},
+            "slices": {"nslices": S, "int8_products": sp, "ms": round(t["slices"], 3),
+                       "slicing_ms": round(t["slicing"], 3),
+                       "gemm_kernel_ms": round(t["slices"] - t["slicing"], 3),
+                       "tflops_equiv": round(fl / (t["slices"] * 1e-3) / 1e12, 2),
+                       "speedup_vs_native": round(t["native"] / t["slices"], 3),
+                       "int8_tops_gemm_kernel": round(sp * fl / ((t["slices"] - t["slicing"]) * 1e-3)
+                                                      / 1e12, 1),
+                       "max_err_vs_oracle": None, "true_err_vs_doubled_precision": None},
+            "native_max_err_vs_oracle": None,
         }
         if args.cpu_budget > 0:
             # CPU-baseline leg: the oracle on sampled full rows and columns (timed), whose values
-            # also state both GPU results' error.
+            # also state every GPU result's error.
             R = sample_lines(m, 4, synth.seed_for(3, phi, 5))
             Sx = sample_lines(n, 4, synth.seed_for(3, phi, 6))
             at = np.ascontiguousarray(synth.view2d(p["A"], m, k, lda)).reshape(-1)
@@ -328,17 +347,24 @@ def split_result(args, torch, mdg):
             cpu_flops += 2.0 * macs  # the denominators' pass is not counted
             cpu_s += dt
             cpu_parts.append(f"phi={phi}: {len(R)} rows + {len(Sx)} columns ({dt:.1f} s)")
-            case["max_err_vs_oracle"] = float(f"{max(max_rel_err(c_split[R, :], ref_r, d_r), max_rel_err(c_split[:, Sx], ref_c, d_c)):.3g}")
-            case["native_max_err_vs_oracle"] = float(f"{max(max_rel_err(c_native[R, :], ref_r, d_r), max_rel_err(c_native[:, Sx], ref_c, d_c)):.3g}")
+
+            def err(c):
+                return float(f"{max(max_rel_err(c[R, :], ref_r, d_r), max_rel_err(c[:, Sx], ref_c, d_c)):.3g}")
+            case["crt"]["max_err_vs_oracle"] = err(outs["crt"])
+            case["slices"]["max_err_vs_oracle"] = err(outs["slices"])
+            case["native_max_err_vs_oracle"] = err(outs["native"])
             R2, S2 = R[:3], Sx[-3:]
             dd_r, _, dd_c, _, _ = oracle_lines(p["A"], p["B"], p["C"], m, n, k, lda, ldb, ldc, 1.0,
                                                1.0, R2, S2, fn="dgemm_dd", at=at)
-            del at
             d_r2, d_c2 = d_r[:3], d_c[:, -3:]
-            case["true_err_vs_doubled_precision"] = float(f"{max(max_rel_err(c_split[R2, :], dd_r, d_r2), max_rel_err(c_split[:, S2], dd_c, d_c2)):.3g}")
+            for name in ("crt", "slices"):
+                c = outs[name]
+                case[name]["true_err_vs_doubled_precision"] = float(
+                    f"{max(max_rel_err(c[R2, :], dd_r, d_r2), max_rel_err(c[:, S2], dd_c, d_c2)):.3g}")
+            del at
         cases.append(case)
-        log(f"[bench] split phi={phi} S={S}: {case}")
-        del c_split, c_native, p
+        log(f"[bench] split phi={phi}: {case}")
+        del outs, p
     cpu = None
     if cpu_s > 0:
         mask, ncpu = host_cores()
@@ -347,28 +373,30 @@ def split_result(args, torch, mdg):
                "affinity": mask, "cpu_count": ncpu, "kind": "oracle",
                "sample": "oracle on sampled full rows and columns of C of each 8192^3 case: " +
                          "; ".join(cpu_parts)}
-    best = max(cases, key=lambda r: r["split_tflops_equiv"])
+    best = max(cases, key=lambda c: c["crt"]["tflops_equiv"])
     return {
         "workload": f"split-precision dgemm NN {m}x{n}x{k}, ld rounded to 8, alpha=beta=1, "
-                    "entries u*2^e, u ~ U[-1,1), e ~ U{-phi..phi}",
+                    "entries u*2^e, u ~ U[-1,1), e ~ U{-phi..phi}; Chinese-remainder scheme "
+                    "(14/15/16 moduli) and slice scheme (7/8/10 slices) against native FP64",
         "unit": "TFLOP/s (FP64-equivalent)",
         "cases": cases,
-        "roofline": {"bound": "mfma", "kernel": f"slice-product GEMM, {best['nslices']} slices "
-                                                f"(phi={best['phi']})",
-                     "achieved": best["int8_tops_gemm_kernel"], "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8)", "frac": best["int8_frac_gemm_kernel"],
-                     "note": "kernel time = whole split call minus the two slicing steps timed "
-                             "alone"},
+        "roofline": {"bound": "mfma", "kernel": f"CRT modular products and recombination, "
+                                                f"{best['crt']['nmoduli']} moduli (phi={best['phi']})",
+                     "achieved": best["crt"]["int8_tops_excl_residues"], "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s (int8)",
+                     "frac": round(best["crt"]["int8_tops_excl_residues"] / INT8_PEAK_TOPS, 4),
+                     "note": "time = whole CRT call minus the two residue steps timed alone (the "
+                             "recombination kernel included)"},
         "cpu_baseline": cpu,
     }
 
 
 def split_workload(args, torch, mdg):
     r = split_result(args, torch, mdg)
-    best = max(r["cases"], key=lambda c: c["split_tflops_equiv"])
+    best = max(r["cases"], key=lambda c: c["crt"]["tflops_equiv"])
     out = {
         "metric": METRIC + " (split-precision leg)",
-        "value": best["split_tflops_equiv"], "unit": "TFLOP/s",
+        "value": best["crt"]["tflops_equiv"], "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i8 slices, f64 recombination",
@@ -528,8 +556,8 @@ def served_result(args, torch, mdg):
                "sample": f"oracle on the first {count} requests of the stream ({t_spent:.1f} s)"}
     return {
         "workload": f"Poisson {args.rate:g} req/s for {args.duration:g} s, m,n,k log-uniform in "
-                    "[32,4096], transposes iid, 80% native, 20% split (phi=8, "
-                    f"{serve.SPLIT_SLICES[8]} slices), HBM budget {args.budget_gb} GiB",
+                    "[32,4096], transposes iid, 80% native, 20% split (phi=8, Chinese-remainder "
+                    f"scheme with {serve.SPLIT_MODULI[8]} moduli), HBM budget {args.budget_gb} GiB",
         "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"], "aggregate_tflops": s["aggregate_tflops"],
         "served": s, "cpu_baseline": cpu,
     }

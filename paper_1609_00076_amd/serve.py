@@ -1,7 +1,8 @@
 """Continuous-batching server for dgemm requests on one GPU.
 
 Requests arrive over time (a seeded Poisson stream), each one GEMM C := alpha*op(A)*op(B) + beta*C
-computed either natively in FP64 or by the split-precision (INT8 slice) path. The server loop:
+computed either natively in FP64 or by the split-precision path (INT8 products recombined by the
+Chinese remainder theorem). The server loop:
 
 1. moves requests whose arrival time has passed into a FIFO admission queue;
 2. admits from the head of the queue while the request's device bytes (operands, plus the
@@ -14,7 +15,7 @@ computed either natively in FP64 or by the split-precision (INT8 slice) path. Th
 4. polls completion events; a finished request releases its bytes to the budget and records its
    latency (arrival to observed completion).
 
-The routing of a request (grouped or single launch, tile class, slice count) depends only on the
+The routing of a request (grouped or single launch, tile class, modulus count) depends only on the
 request itself, so its result is the same alone and in any mix.
 """
 from __future__ import annotations
@@ -28,9 +29,10 @@ import numpy as np
 
 GROUP_MAX_DIM = 512
 GROUP_THRESHOLD = 40   # grouped tile class 1 (32x32) when min(m, n) < this
-# Slices per exponent spread phi for requests with k down to 32: at phi = 8 a row of 32 entries
-# needs 9 slices to keep max |C - Cref| / (|A||B|)_ij under 1e-13 (8 suffice from k ~ 256 on).
-SPLIT_SLICES = {0: 7, 8: 9}
+# Split requests run the Chinese-remainder split (one INT8 product per modulus). Moduli per
+# exponent spread phi for requests with k down to 32: at phi = 8 a row of 32 entries needs 16 to keep
+# max |C - Cref| / (|A||B|)_ij under 1e-13 (15 suffice at k = 2048 and beyond).
+SPLIT_MODULI = {0: 14, 8: 16}
 
 
 @dataclass
@@ -188,8 +190,8 @@ class Server:
     def request_bytes(self, req):
         nb = req.operand_bytes()
         if req.kind == "split":
-            nb += self.mdg.mdg_dgemm_split_workspace_size(req.m, req.n, req.k,
-                                                          SPLIT_SLICES[req.phi])
+            nb += self.mdg.mdg_dgemm_crt_workspace_size(req.m, req.n, req.k,
+                                                        SPLIT_MODULI[req.phi])
         return nb
 
     def _fill(self, t, req):
@@ -211,8 +213,8 @@ class Server:
                 self._fill(t, req)
                 ops[x] = t
             if req.kind == "split":
-                nb = self.mdg.mdg_dgemm_split_workspace_size(req.m, req.n, req.k,
-                                                             SPLIT_SLICES[req.phi])
+                nb = self.mdg.mdg_dgemm_crt_workspace_size(req.m, req.n, req.k,
+                                                           SPLIT_MODULI[req.phi])
                 ops["W"] = torch.empty(max(256, nb), dtype=torch.uint8, device="cuda")
         return ops
 
@@ -226,8 +228,8 @@ class Server:
     def launch_single(self, req, ops, stream):
         args = self.gemm_args(req, ops)
         if req.kind == "split":
-            S = SPLIT_SLICES[req.phi]
-            st = self.mdg.mdg_dgemm_split(*args, S, ops["W"], ops["W"].numel(), stream=stream)
+            st = self.mdg.mdg_dgemm_crt(*args, SPLIT_MODULI[req.phi], ops["W"], ops["W"].numel(),
+                                        stream=stream)
         else:
             st = self.mdg.mdg_dgemm(*args, stream=stream)
         if st:

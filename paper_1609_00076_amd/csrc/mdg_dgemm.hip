@@ -10,9 +10,11 @@
 //   loops 2 and 1 (jr, ir)   -> the waves of a workgroup, each owning a wm x wn sub-tile;
 //   loop 0 (the micro-kernel)-> chains of v_mfma_f64_16x16x4_f64, each one four rank-1 updates of a
 //                               16x16 block held in accumulator registers (section 4.3).
-// Fringes (section 2.4: m, n, k not multiples of the block sizes) are handled in the kernel: loads
-// outside the logical matrix read a clamped in-bounds address and are replaced by zero, and stores
-// outside C are masked, so the padding rows of every operand are never read or written.
+// Fringes (section 2.4: m, n, k not multiples of the block sizes) are handled in the kernel: an
+// operand is read through a buffer resource whose byte range is the operand's extent, so a load past
+// the end returns zero without touching memory; loads of padding rows or of k beyond the logical
+// depth are zeroed (or masked out of the product) by the row and depth masks; stores outside C are
+// masked. The padding rows of every operand are thus never used and never written.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -525,20 +527,29 @@ dgemm_wave_kernel(GemmArgs g, int tiles_m, int tiles_n) {
 // 16c..16c+15) in substep e of pair h is 8h + 2c + e; both operands use this order, which only
 // permutes the terms of each panel's sum.
 // ------------------------------------------------------------------------------------------------
-template <int MT_, int NT_, int WM_, int WN_, int STAGES_, int MIN_WAVES_PER_EU_, int SCHED_ = 0>
+template <int MT_, int NT_, int WM_, int WN_, int STAGES_, int MIN_WAVES_PER_EU_, int SCHED_ = 0,
+          int KS_ = 1>
 struct RingCfg {
   static constexpr int MT = MT_, NT = NT_, KT = 16, WM = WM_, WN = WN_, STAGES = STAGES_;
   // Instruction order inside a k-step. 0: each panel's fragment reads strictly before the MFMAs
   // they overlap; 1: MFMAs interleaved one by one with the direct loads and fragment reads, so
   // that the matrix pipe restarts at once after a barrier and LDS traffic is spread out.
   static constexpr int SCHED = SCHED_;
+  // Wave groups splitting k inside the workgroup: group g multiplies the panels p with
+  // p % KS == g of the tile's k-loop, each group an independent grid of WAVES_G waves with its
+  // own part of every LDS stage, all groups in step at the same barriers. A stage then holds KS
+  // panels, so each barrier covers KS panels of MFMA work and every SIMD runs KS waves. At the
+  // end the groups add their partial tiles through LDS in a fixed order (the result does not
+  // depend on timing) and each writes its share of C.
+  static constexpr int KS = KS_;
   // Tile-rows per column group of the XCD-aware tile order: the 32 tiles resident on an XCD then
   // span GROUP tile-rows and 32 / GROUP tile-columns; 4 x 8 tiles of 256 x 128 touch the fewest
   // rows of op(A) plus columns of op(B) per k-panel (1024 + 1024).
   static constexpr int GROUP = MT > NT ? 4 : 8;
   static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
-  static constexpr int WAVES = WAVES_M * WAVES_N;
+  static constexpr int WAVES_G = WAVES_M * WAVES_N;  // waves per k-group
+  static constexpr int WAVES = WAVES_G * KS;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int BM = WM / 16, BN = WN / 16;
   static constexpr int PAIRS = KT / 8;  // k-pairs of MFMA substeps per panel
@@ -546,16 +557,19 @@ struct RingCfg {
   // direct loads fill two k-rows at once and use the XOR placement of kmaj_index instead.
   static constexpr int ROW_A = MT == 64 ? 64 : MT + 8, ROW_B = NT == 64 ? 64 : NT + 8;
   static constexpr int STAGE_A = KT * ROW_A, STAGE_B = KT * ROW_B;
-  static constexpr int STAGE = STAGE_A + STAGE_B;
-  static constexpr int LDS_DOUBLES = STAGES * STAGE;
-  static constexpr int A_LOADS = MT * KT / 128 / WAVES, B_LOADS = NT * KT / 128 / WAVES;
+  static constexpr int STAGE = STAGE_A + STAGE_B;  // one panel of one k-group
+  static constexpr int SUPER = KS * STAGE;         // one ring slot: a panel per k-group
+  static constexpr int LDS_DOUBLES = STAGES * SUPER;
+  static constexpr int A_LOADS = MT * KT / 128 / WAVES_G, B_LOADS = NT * KT / 128 / WAVES_G;
   static constexpr int LOADS = A_LOADS + B_LOADS;  // direct loads per wave per panel
   static_assert((MT % 128 == 0 || MT == 64) && (NT % 128 == 0 || NT == 64),
                 "k-major chunks are 128-row pieces of a k-row, or two k-rows of a 64-row tile");
-  static_assert((MT * KT / 128) % WAVES == 0 && (NT * KT / 128) % WAVES == 0, "chunk split");
+  static_assert((MT * KT / 128) % WAVES_G == 0 && (NT * KT / 128) % WAVES_G == 0, "chunk split");
   static_assert(MT % WM == 0 && NT % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave grid");
   static_assert(STAGES >= 2 && STAGES <= 4 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
   static_assert(THREADS <= 1024, "workgroup size");
+  static_assert(KS == 1 || (KS == 2 && BN % 2 == 0 && MT * NT <= LDS_DOUBLES),
+                "two k-groups share the column blocks of the epilogue through the LDS ring");
 };
 
 __device__ __forceinline__ int ring_swz(int row) { return (row & 7) ^ ((row >> 3) & 1); }
@@ -622,7 +636,7 @@ __device__ __forceinline__ void sched_mfmas_then() {
 template <class R, int ROWS, int ROW, bool CONTIG_K>
 __device__ __forceinline__ void ring_map(int wave, int lane, int u, int64_t ld, uint32_t& off,
                                          int& lds) {
-  const int c = wave + R::WAVES * u;
+  const int c = wave + R::WAVES_G * u;
   if constexpr (!CONTIG_K && ROWS == 64) {
     // chunk c holds k-rows 2c (lanes 0-31) and 2c+1 (lanes 32-63); lane l writes doubles
     // 2(l & 31), +1 of its k-row, which kmaj_index assigns to rows i, i+1 below
@@ -644,12 +658,14 @@ __device__ __forceinline__ void ring_map(int wave, int lane, int u, int64_t ld, 
   }
 }
 
-// Zero the entries with k-index >= k_left of one stage (ragged last panel).
+// Zero the entries with k-index >= k_left of one panel (ragged last panel); the threads of one
+// k-group (thread index gt of R::WAVES_G * 64) share the work.
 template <class R, bool TA, bool TB>
-__device__ __forceinline__ void ring_mask_tail(double* st, int k_left) {
+__device__ __forceinline__ void ring_mask_tail(double* st, int k_left, int gt) {
+  constexpr int kStride = R::WAVES_G * 64;
   double* As = st;
   double* Bs = st + R::STAGE_A;
-  for (int e = threadIdx.x; e < R::MT * R::KT; e += R::THREADS) {
+  for (int e = gt; e < R::MT * R::KT; e += kStride) {
     if (!TA) {
       const int q = e / R::MT, i = e % R::MT;
       if (q >= k_left) As[kmaj_index<R::MT, R::ROW_A>(q, i)] = 0.0;
@@ -657,7 +673,7 @@ __device__ __forceinline__ void ring_mask_tail(double* st, int k_left) {
     else { const int i = e / R::KT, q = e % R::KT;
            if (q >= k_left) As[i * R::KT + 2 * ((q >> 1) ^ ring_swz(i)) + (q & 1)] = 0.0; }
   }
-  for (int e = threadIdx.x; e < R::NT * R::KT; e += R::THREADS) {
+  for (int e = gt; e < R::NT * R::KT; e += kStride) {
     if (TB) {
       const int q = e / R::NT, j = e % R::NT;
       if (q >= k_left) Bs[kmaj_index<R::NT, R::ROW_B>(q, j)] = 0.0;
@@ -674,7 +690,10 @@ template <class R, bool TA, bool TB, int TRI = 0>
 __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, double* smem) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wave_all = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = R::KS == 1 ? 0 : wave_all / R::WAVES_G;  // k-group
+  const int wave = R::KS == 1 ? wave_all : wave_all % R::WAVES_G;
+  const int gtid = R::KS == 1 ? tid : tid - grp * R::WAVES_G * 64;
   const int wave_m = wave % R::WAVES_M, wave_n = wave / R::WAVES_M;
   const int l16 = lane & 15, lq = lane >> 4;
   const int64_t row0 = (int64_t)tm * R::MT, col0 = (int64_t)tn * R::NT;
@@ -689,16 +708,25 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
   for (int u = 0; u < R::B_LOADS; ++u)
     ring_map<R, R::NT, R::ROW_B, !TB>(wave, lane, u, g.ldb, b_off[u], b_lds[u]);
 
-  const int64_t a_org = TA ? row0 * g.lda : row0;
-  const int64_t a_step = TA ? (int64_t)R::KT : (int64_t)R::KT * g.lda;
-  const int64_t b_org = TB ? col0 : col0 * g.ldb;
-  const int64_t b_step = TB ? (int64_t)R::KT * g.ldb : (int64_t)R::KT;
+  // Ring slot p holds k-panel KS * p + g of group g at offset g * STAGE; num_k counts slots.
+  constexpr int KD = R::KS * R::KT;  // k-depth of one ring slot
+  const int64_t a_gk = TA ? (int64_t)R::KT : (int64_t)R::KT * g.lda;  // one panel along k
+  const int64_t b_gk = TB ? (int64_t)R::KT * g.ldb : (int64_t)R::KT;
+  const int64_t a_org = (TA ? row0 * g.lda : row0) + grp * a_gk;
+  const int64_t a_step = R::KS * a_gk;
+  const int64_t b_org = (TB ? col0 : col0 * g.ldb) + grp * b_gk;
+  const int64_t b_step = R::KS * b_gk;
+  double* const gsm = smem + grp * R::STAGE;  // this group's part of slot 0
 
-  const int num_k = (g.alpha == 0.0) ? 0 : (int)((g.k + R::KT - 1) / R::KT);
-  const int k_left_last = (int)(g.k - (int64_t)(num_k - 1) * R::KT);  // 1..KT
+  const int num_k = (g.alpha == 0.0) ? 0 : (int)((g.k + KD - 1) / KD);
+  const int k_left_last = (int)(g.k - (int64_t)(num_k - 1) * KD);  // 1..KD
+  // k-entries of this group's panel in the last slot: KT, fewer, or none (then the whole panel
+  // is masked; its loads start past the operand's end or are masked like any k-tail)
+  const int k_left_grp =
+      R::KS == 1 ? k_left_last : min(max(k_left_last - grp * R::KT, 0), R::KT);
 
   auto issue = [&](int p) {
-    double* st = smem + (p % R::STAGES) * R::STAGE;
+    double* st = gsm + (p % R::STAGES) * R::SUPER;
     const int64_t ao = a_org + p * a_step, bo = b_org + p * b_step;
     const rsrc_t ra = make_rsrc(g.A + ao, g.ext_a - ao);
     const rsrc_t rb = make_rsrc(g.B + bo, g.ext_b - bo);
@@ -787,13 +815,13 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     for (int p = 0; p < pre; ++p) issue(p);
     wait_panels<R::LOADS, R::STAGES - 1>(pre - 1);
     ring_barrier();
-    if (num_k == 1 && k_left_last < R::KT) {
-      ring_mask_tail<R, TA, TB>(smem, k_left_last);
+    if (num_k == 1 && k_left_last < KD) {
+      ring_mask_tail<R, TA, TB>(gsm, k_left_grp, gtid);
       __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
       ring_barrier();
     }
     d2 fa0[R::BM], fb0[R::BN], fa1[R::BM], fb1[R::BN];
-    read_frags(smem, 0, fa0, fb0);
+    read_frags(gsm, 0, fa0, fb0);
     // 16-byte fragment reads per read_frags: one per block (row-major), two per pair of blocks
     // (k-major).
     constexpr int kReads = R::BM + R::BN;
@@ -802,7 +830,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     // barrier is not the last one (which may need its k-tail masked), so the body has a single
     // path. Pair 1 of panel t is multiplied after the barrier that ends the panel.
     for (; t + R::STAGES < num_k && t + 2 < num_k; ++t) {
-      const double* st = smem + (t % R::STAGES) * R::STAGE;
+      const double* st = gsm + (t % R::STAGES) * R::SUPER;
       read_frags(st, 1, fa1, fb1);
       if (R::SCHED == 0) __builtin_amdgcn_sched_barrier(0);  // reads ahead of the MFMAs below
       mfma_pair(fa0, fb0);
@@ -810,7 +838,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
       wait_vm_lgkm0<(R::STAGES - 2) * R::LOADS>();
       ring_barrier();
       issue(t + R::STAGES);
-      read_frags(smem + ((t + 1) % R::STAGES) * R::STAGE, 0, fa0, fb0);
+      read_frags(gsm + ((t + 1) % R::STAGES) * R::SUPER, 0, fa0, fb0);
       if (R::SCHED == 0) __builtin_amdgcn_sched_barrier(0);
       mfma_pair(fa1, fb1);
       if (R::SCHED == 1) {
@@ -820,7 +848,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     }
     // Drain: the last panels are loaded or in flight; the last one may need its k-tail masked.
     for (; t < num_k - 1; ++t) {
-      const double* st = smem + (t % R::STAGES) * R::STAGE;
+      const double* st = gsm + (t % R::STAGES) * R::SUPER;
       read_frags(st, 1, fa1, fb1);
       __builtin_amdgcn_sched_barrier(0);
       mfma_pair(fa0, fb0);
@@ -828,9 +856,9 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
       wait_panels<R::LOADS, R::STAGES - 2>(last_issued - (t + 1));
       ring_barrier();
       if (t + R::STAGES < num_k) issue(t + R::STAGES);
-      const double* nst = smem + ((t + 1) % R::STAGES) * R::STAGE;
-      if (t + 1 == num_k - 1 && k_left_last < R::KT) {
-        ring_mask_tail<R, TA, TB>(const_cast<double*>(nst), k_left_last);
+      const double* nst = gsm + ((t + 1) % R::STAGES) * R::SUPER;
+      if (t + 1 == num_k - 1 && k_left_last < KD) {
+        ring_mask_tail<R, TA, TB>(const_cast<double*>(nst), k_left_grp, gtid);
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
         ring_barrier();
       }
@@ -838,9 +866,40 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
       __builtin_amdgcn_sched_barrier(0);
       mfma_pair(fa1, fb1);
     }
-    read_frags(smem + ((num_k - 1) % R::STAGES) * R::STAGE, 1, fa1, fb1);
+    read_frags(gsm + ((num_k - 1) % R::STAGES) * R::SUPER, 1, fa1, fb1);
     mfma_pair(fa0, fb0);
     mfma_pair(fa1, fb1);
+  }
+
+  // Two k-groups: group g keeps column blocks [g BN/2, (g+1) BN/2) of its wave's tile and hands
+  // the others to the group that keeps them, through the (drained) LDS ring. Each entry becomes
+  // (group 0's sum) + (group 1's sum), the same value whichever group adds it.
+  constexpr int kHalf = R::BN / R::KS;
+  if constexpr (R::KS == 2) {
+    constexpr int kPer = R::BM * kHalf * 4 * 64;  // doubles one wave hands over
+    ring_barrier();  // every wave is past its last fragment read; no direct load is in flight
+    double* mine = smem + (grp * R::WAVES_G + wave) * kPer;
+    const double* theirs = smem + ((1 - grp) * R::WAVES_G + wave) * kPer;
+#pragma unroll
+    for (int bj = 0; bj < R::BN; ++bj) {
+      if (bj / kHalf == grp) continue;
+#pragma unroll
+      for (int bi = 0; bi < R::BM; ++bi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          mine[((bi * kHalf + bj % kHalf) * 4 + r) * 64 + lane] = acc[bi][bj][r];
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    ring_barrier();
+#pragma unroll
+    for (int bj = 0; bj < R::BN; ++bj) {
+      if (bj / kHalf != grp) continue;
+#pragma unroll
+      for (int bi = 0; bi < R::BM; ++bi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[bi][bj][r] += theirs[((bi * kHalf + bj % kHalf) * 4 + r) * 64 + lane];
+    }
   }
 
   // Epilogue: C(i,j) := alpha*acc + beta*C(i,j); with beta == 0 the old C is not read. Block bi
@@ -856,6 +915,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
   };
 #pragma unroll
   for (int bj2 = 0; bj2 < R::BN; ++bj2) {
+    if (bj2 / kHalf != grp) continue;
     double cb[R::BM][4];
     if (beta != 0.0) {
 #pragma unroll
@@ -974,6 +1034,9 @@ using Ring128x64 = RingCfg<128, 64, 32, 32, 3, 4, 1>;   // 8 waves of 32x32, 3 s
 using Ring128x256wi = RingCfg<128, 256, 64, 64, 3, 2, 1>;  // 8 waves of 64x64 on a wide tile, 3 stages
 using Ring256x128t = RingCfg<256, 128, 128, 32, 3, 2, 1>;  // 8 waves of 128x32, 3 stages
 using Ring128x256t = RingCfg<128, 256, 128, 32, 3, 2, 1>;  // 8 waves of 128x32 on a wide tile
+// Two k-groups of 4 waves of 32x32 on a 64x64 tile, 4 stages: two waves per SIMD with one
+// workgroup per CU.
+using Ring64k2 = RingCfg<64, 64, 32, 32, 4, 2, 1, 2>;
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -990,6 +1053,7 @@ struct Variant {
                          // C streams in and out); 0 keeps the variant out of the choice for
                          // k <= kShortK
   KernelFn fn[2][2];  // [transa][transb]
+  int ks;             // k-groups per workgroup (ring configurations; 1 elsewhere)
 };
 
 template <class C>
@@ -1015,7 +1079,8 @@ constexpr Variant make_ring_variant(const char* name, Eff e, int short_k = 0) {
   return Variant{name, R::MT, R::NT, R::KT, R::THREADS, wgs > 0 ? wgs : 1,
                  {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
                  {{dgemm_ring_kernel<R, false, false>, dgemm_ring_kernel<R, false, true>},
-                  {dgemm_ring_kernel<R, true, false>, dgemm_ring_kernel<R, true, true>}}};
+                  {dgemm_ring_kernel<R, true, false>, dgemm_ring_kernel<R, true, true>}},
+                 R::KS};
 }
 
 template <class C>
@@ -1028,7 +1093,8 @@ constexpr Variant make_variant(const char* name, Eff e, int short_k = 0) {
                  resident_wgs<C>() > 0 ? resident_wgs<C>() : 1,
                  {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
                  {{dgemm_mfma_kernel<C, false, false>, dgemm_mfma_kernel<C, false, true>},
-                  {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}}};
+                  {dgemm_mfma_kernel<C, true, false>, dgemm_mfma_kernel<C, true, true>}},
+                 1};
 }
 
 // The single-GEMM form of the wave tiles: 64x64 per workgroup as four independent 32x32 wave
@@ -1036,7 +1102,8 @@ constexpr Variant make_variant(const char* name, Eff e, int short_k = 0) {
 constexpr Variant make_wave_variant(const char* name, Eff e, int short_k = 0) {
   return Variant{name, 64, 64, kWK, 256, 4, {{e.nn, e.nt}, {e.tn, e.tt}}, short_k,
                  {{dgemm_wave_kernel<false, false>, dgemm_wave_kernel<false, true>},
-                  {dgemm_wave_kernel<true, false>, dgemm_wave_kernel<true, true>}}};
+                  {dgemm_wave_kernel<true, false>, dgemm_wave_kernel<true, true>}},
+                 1};
 }
 
 // Efficiencies are the measured TFLOP/s of each variant at m = n = k = 8192..16384 divided by
@@ -1055,6 +1122,7 @@ const Variant kVariants[] = {
     make_ring_variant<Ring256x128t>("ring_f64_256x128x16_w128x32_s3_il", Eff(935, 939, 946, 945)),
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
     make_wave_variant("wave_f64_64x64x8_w32x32", 0),
+    make_ring_variant<Ring64k2>("ringk2_f64_64x64x16_w32x32_s4", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1262,7 +1330,8 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // the earlier entry.
 // For k <= kShortK the GEMM is bound by the old C streaming through HBM rather than by the
 // MFMAs, and the variants are ranked by their efficiency measured on such a shape (which already
-// includes the epilogue).
+// includes the epilogue). Variants with two k-groups have no efficiency of their own: one replaces
+// the chosen one-group variant of the same tile when the grid is a single round (below).
 constexpr double kTileOverheadK = 128.0;
 constexpr int64_t kShortK = 256;
 
@@ -1285,6 +1354,15 @@ int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
       best = v;
       best_cost = cost;
     }
+  }
+  // A grid of at most one workgroup per CU leaves each SIMD one wave of a one-group tile; the
+  // k-split configuration of the same tile runs two per SIMD there (measured at 1024^3: 8% faster;
+  // with two or more tiles per CU the one-group form is as fast or faster).
+  const Variant& b = kVariants[best];
+  if (!short_k && b.ks == 1 &&
+      ceil_div(m, b.mt) * ceil_div(n, b.nt) <= kCUs) {
+    for (int v = 0; v < kNumVariants; ++v)
+      if (kVariants[v].ks == 2 && kVariants[v].mt == b.mt && kVariants[v].nt == b.nt) return v;
   }
   return best;
 }

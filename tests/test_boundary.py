@@ -133,7 +133,8 @@ def test_leading_dimension_offset_guard_is_host_side_and_exact():
 def test_sweep_variant_choice():
     """The measured choice for the sweep shapes (each a variant whose efficiency was measured on the
     GPU for that transpose case): 256x128 or 128x256 ring tiles from 4096 up, smaller ring tiles for
-    1024 to 4099, the register-staged 128x64 tile for the HBM-bound k = 64 case."""
+    2048 to 4099, the k-split 64x64 ring tile for 1024 (one tile per CU), the register-staged
+    128x64 tile for the HBM-bound k = 64 case."""
     def name(ta, tb, m, n, k):
         return mdg.mdg_variant_name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
     want = {"NN": "ring_f64_128x256x16_w128x32_s3_il", "NT": "ring_f64_128x256x16_w64x64_s3_il",
@@ -144,7 +145,7 @@ def test_sweep_variant_choice():
                 assert name(ta, tb, size, size, size) == want[ta + tb]
     for ta in "NT":
         for tb in "NT":
-            assert name(ta, tb, 1024, 1024, 1024).startswith("ring_f64_64x64x16")
+            assert name(ta, tb, 1024, 1024, 1024) == "ringk2_f64_64x64x16_w32x32_s4"
             assert name(ta, tb, 2048, 2048, 2048).startswith("ring_f64_128x")
             assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"
 
@@ -170,6 +171,20 @@ def test_every_variant_is_reachable():
     for v in range(nv):
         name = mdg.mdg_variant_name(v)
         assert v in chosen or name in grouped, f"variant {v} ({name}) is never used"
+
+
+def test_single_round_grids_take_the_k_split_tile():
+    """A grid of at most one 64x64 tile per CU (256 CUs) with k above the short-k bound runs the
+    k-split configuration of that tile; more tiles, short k or other tiles keep the one-group
+    choice."""
+    name = mdg.mdg_variant_name
+    for ta in "NT":
+        for tb in "NT":
+            for m, n, k in ((1024, 1024, 1024), (1000, 1000, 300), (512, 2048, 4096)):
+                assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
+            for m, n, k in ((1024, 1024, 256), (1025, 1024, 1024), (2048, 2048, 2048),
+                            (8192, 8192, 8192)):
+                assert not name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
 
 
 # ---- level-3 entry points: checks and refusals that return before any HIP call ----------------

@@ -81,6 +81,74 @@ def build_problems(torch, shapes_filter=None):
     return probs
 
 
+def sweep_shapes():
+    """(transa, transb, m, n, k) of the sweep problems in build_problems' launch order."""
+    out = [dict(transa=tr[0], transb=tr[1], m=size, n=size, k=size) for size in SQUARES for tr in TRANS]
+    m, n, k = SKINNY
+    return out + [dict(transa=tr[0], transb=tr[1], m=m, n=n, k=k) for tr in TRANS]
+
+
+def read_counter(run_dir, counter):
+    """{dispatch id: (kernel name, value)} from a rocprofv3 --pmc csv directory."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(run_dir, "*counter_collection.csv")):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, v = out.get(d, (r["Kernel_Name"], 0.0))
+            out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def traffic_from(dirs, copy_bytes, mdg):
+    """Write TRAFFIC_FILE from four rocprofv3 --pmc runs: FETCH_SIZE and WRITE_SIZE of one sweep
+    step (bench.py --steps 1 --warmup 0 --cpu-budget 0), then of the copy calibration
+    (bench.py --copy-calibration copy_bytes). The sweep's GEMM dispatches are matched to its
+    problems in launch order; each counter (KiB per dispatch) is scaled by the factor that maps its
+    reading for one copy of copy_bytes to the bytes the copy reads (FETCH) or writes (WRITE)."""
+    f_dir, w_dir, cf_dir, cw_dir = dirs
+    def scale(run_dir, counter):
+        vals = [v for _, (name, v) in sorted(read_counter(run_dir, counter).items())]
+        per = sorted(vals[-3:])[1] * 1024.0  # the median of the three copies (the last launches)
+        return copy_bytes / per
+    fs, ws = scale(cf_dir, "FETCH_SIZE"), scale(cw_dir, "WRITE_SIZE")
+    gemm = ("dgemm_ring_kernel", "dgemm_mfma_kernel", "dgemm_wave_kernel")
+    probs = sweep_shapes()
+    per = {}
+    for counter, sc in (("FETCH_SIZE", fs), ("WRITE_SIZE", ws)):
+        rows = [v for _, (name, v) in sorted(read_counter(f_dir if counter == "FETCH_SIZE" else w_dir,
+                                                             counter).items())
+                if any(g in name for g in gemm)]
+        if len(rows) != len(probs):
+            raise SystemExit(f"{counter}: {len(rows)} GEMM dispatches for {len(probs)} problems")
+        for p, v in zip(probs, rows):
+            d = per.setdefault(kernel_key(mdg, p), dict(meas=0.0, alg=0.0, n=0, shapes=set()))
+            d["meas"] += v * 1024.0 * sc
+            if counter == "FETCH_SIZE":
+                d["alg"] += hbm_bytes(p)
+                d["n"] += 1
+                d["shapes"].add(f"{p['m']}x{p['n']}x{p['k']}")
+    out = {"source_sha": source_hash(), "workload": out_workload(probs), "fetch_scale": fs,
+           "write_scale": ws,
+           "bytes_per_launch": {k: d["meas"] / d["n"] for k, d in sorted(per.items())},
+           "algorithmic_bytes_per_launch": {k: d["alg"] / d["n"] for k, d in sorted(per.items())},
+           "note": "FETCH_SIZE + WRITE_SIZE per dispatch (KiB x 1024), each times the factor that "
+                   "maps the counter's reading of a device copy to the bytes it moves; averaged "
+                   "over the kernel's launches in one sweep step"}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"FETCH_SIZE x {fs:.4f}, WRITE_SIZE x {ws:.4f}")
+    print("| Kernel [transposes] | launches | measured GB | algorithmic GB | ratio |")
+    print("|---|---|---|---|---|")
+    for k, d in sorted(per.items()):
+        meas, alg = d["meas"] / d["n"], d["alg"] / d["n"]
+        print(f"| `{k}` | {', '.join(sorted(d['shapes']))} | {meas / 1e9:.3f} | {alg / 1e9:.3f} | "
+              f"{meas / alg:.1f} |")
+
+
 def out_workload(probs):
     return sorted({f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}" for p in probs})
 
@@ -822,6 +890,10 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="served: seconds of arrivals")
     ap.add_argument("--budget-gb", type=int, default=64, help="served: HBM budget in GiB")
     ap.add_argument("--tune-db", default="", help="grouped: tuning database path")
+    ap.add_argument("--traffic-from", default="", metavar="F,W,CF,CW",
+                    help="write profiles/hbm_traffic.json from four rocprofv3 --pmc output "
+                         "directories (sweep FETCH_SIZE, sweep WRITE_SIZE, copy FETCH_SIZE, copy "
+                         "WRITE_SIZE; the copy of --copy-calibration bytes); no GPU needed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times (the "
                          "reference kernel for scaling HBM byte counters), then exit")
@@ -837,6 +909,9 @@ def main():
 
     import paper_1609_00076_amd as mdg
     mdg.load()
+    if args.traffic_from:
+        traffic_from(args.traffic_from.split(","), args.copy_calibration or (1 << 30), mdg)
+        return
     if not torch.cuda.is_available():
         print("bench.py: no HIP device visible", file=sys.stderr)
         sys.exit(1)

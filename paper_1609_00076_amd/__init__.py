@@ -7,7 +7,7 @@ package is the thin Python binding (ctypes); torch supplies device memory and
 streams only.
 """
 from .binding import (MDG_ERR_DEVICE, MDG_ERR_HIP, MDG_ERR_SCRATCH, MDG_ERR_SIZE, MDG_ERR_VARIANT,
-                      MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, load,
+                      MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, gemm2d, gemm2d_args, load,
                       mdg_crt_bits, mdg_crt_max_moduli, mdg_crt_residues, mdg_dgemm, mdg_dgemm_crt,
                       mdg_dgemm_crt_workspace_size,
                       mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_split, mdg_dgemm_split_noalloc,
@@ -20,7 +20,7 @@ from .binding import (MDG_ERR_DEVICE, MDG_ERR_HIP, MDG_ERR_SCRATCH, MDG_ERR_SIZE
                       mdg_version)
 
 __all__ = ["MDG_ERR_DEVICE", "MDG_ERR_HIP", "MDG_ERR_SCRATCH", "MDG_ERR_SIZE", "MDG_ERR_VARIANT",
-           "MDG_SCHEDULE_LPT", "MDG_SCHEDULE_NATURAL", "MdgError", "dgemm", "load",
+           "MDG_SCHEDULE_LPT", "MDG_SCHEDULE_NATURAL", "MdgError", "dgemm", "gemm2d", "gemm2d_args", "load",
            "mdg_crt_bits", "mdg_crt_max_moduli", "mdg_crt_residues", "mdg_dgemm", "mdg_dgemm_crt",
            "mdg_dgemm_crt_workspace_size",
            "mdg_dgemm_ex", "mdg_dgemm_grouped", "mdg_dgemm_split", "mdg_dgemm_split_noalloc",

@@ -445,3 +445,58 @@ def dgemm(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream=N
     st = mdg_dgemm_ex(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, stream)
     if st:
         raise MdgError(st)
+
+
+def _layout(shape, strides, name):
+    """(stored transposed?, ld) of a 2-D tensor whose elements are unit-stride along one dimension.
+
+    A tensor of shape (r, c) with strides (1, ld) is the column-major r x c matrix with leading
+    dimension ld; strides (ld, 1) make it the column-major c x r matrix (its transpose) with
+    leading dimension ld. A dimension of size 1 places no constraint on its stride."""
+    r, c = shape
+    s0, s1 = strides
+    if s0 == 1 or r <= 1:
+        if c <= 1 or s1 >= max(1, r):
+            return False, max(1, r) if c <= 1 else s1
+    if s1 == 1 or c <= 1:
+        if r <= 1 or s0 >= max(1, c):
+            return True, max(1, c) if r <= 1 else s0
+    raise ValueError(f"{name}: strides {tuple(strides)} of shape {tuple(shape)} are neither "
+                     "column-major (1, ld >= rows) nor row-major (ld >= cols, 1)")
+
+
+def gemm2d_args(a_shape, a_strides, b_shape, b_strides, c_shape, c_strides, transa="N",
+                transb="N"):
+    """The dgemm call (transa, transb, m, n, k, lda, ldb, ldc, swap) for 2-D operands given by
+    shape and strides, each unit-stride along one dimension. op(A) is m x k, op(B) k x n, C m x n.
+    A row-major operand is passed as the column-major storage of its transpose with the transpose
+    flag flipped. A row-major C is computed as C^T = op(B)^T op(A)^T (swap True: the first operand
+    of the call is B)."""
+    ta, tb = _is_trans(transa), _is_trans(transb)
+    if len(a_shape) != 2 or len(b_shape) != 2 or len(c_shape) != 2:
+        raise ValueError("gemm2d takes 2-D tensors")
+    m, k = (a_shape[1], a_shape[0]) if ta else tuple(a_shape)
+    kb, n = (b_shape[1], b_shape[0]) if tb else tuple(b_shape)
+    if kb != k or tuple(c_shape) != (m, n):
+        raise ValueError(f"shapes do not match: op(A) {m}x{k}, op(B) {kb}x{n}, C {tuple(c_shape)}")
+    a_t, lda = _layout(a_shape, a_strides, "A")
+    b_t, ldb = _layout(b_shape, b_strides, "B")
+    c_t, ldc = _layout(c_shape, c_strides, "C")
+    fa, fb = ta != a_t, tb != b_t  # flag for the column-major storage actually passed
+    if not c_t:
+        return ("T" if fa else "N", "T" if fb else "N", m, n, k, lda, ldb, ldc, False)
+    # C stored as C^T (n x m column-major): C^T = op(B)^T op(A)^T
+    return ("N" if fb else "T", "N" if fa else "T", n, m, k, ldb, lda, ldc, True)
+
+
+def gemm2d(A, B, C, alpha=1.0, beta=0.0, transa="N", transb="N", stream=None, variant=-1):
+    """C := alpha*op(A)*op(B) + beta*C on 2-D float64 device tensors, each column-major
+    (strides (1, ld)) or row-major (strides (ld, 1)), sizes and leading dimensions taken from the
+    tensors (see gemm2d_args). Raises MdgError on a non-zero status; returns C."""
+    ta, tb, m, n, k, lda, ldb, ldc, swap = gemm2d_args(
+        tuple(A.shape), A.stride(), tuple(B.shape), B.stride(), tuple(C.shape), C.stride(),
+        transa, transb)
+    first, second = (B, A) if swap else (A, B)
+    dgemm(ta, tb, m, n, k, alpha, first, lda, second, ldb, beta, C, ldc, stream=stream,
+          variant=variant)
+    return C

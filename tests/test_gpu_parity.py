@@ -292,3 +292,36 @@ def test_leading_dimensions_at_the_offset_limit():
     big = [v for v in VARIANTS[1:] if mdg.mdg_variant_name(v) == "ring_f64_256x128x16_w128x32_s3_il"][0]
     dC = torch.from_numpy(c0.T.copy().ravel()).cuda()
     assert mdg.mdg_dgemm_ex(big, "N", "N", m, n, k, 1.5, dA, ld + 20, dB_small, k, 0.5, dC, m) == -4
+
+
+@pytest.mark.parametrize("layouts", ["colcolcol", "rowrowrow", "colrowcol", "rowcolrow"])
+@pytest.mark.parametrize("trans", TRANS)
+def test_gemm2d_tensor_form(layouts, trans):
+    """gemm2d on 2-D device tensors (column-major with padded ld, or row-major) equals the
+    oracle's result of the same GEMM bit for bit on integer data."""
+    import paper_1609_00076_amd as mdg
+    import torch
+    la, lb, lc = layouts[:3], layouts[3:6], layouts[6:]
+    m, n, k = 150, 97, 70
+    g = synth.rng(synth.seed_for(31, 0, 0))
+    opa = g.integers(-8, 9, (m, k)).astype(np.float64)
+    opb = g.integers(-8, 9, (k, n)).astype(np.float64)
+    c0 = g.integers(-8, 9, (m, n)).astype(np.float64)
+
+    def dev(x, layout, pad):
+        r, c = x.shape
+        if layout == "col":
+            base = torch.full((c, r + pad), float("nan"), dtype=torch.float64, device="cuda")
+            view = base[:, :r].t()
+        else:
+            base = torch.full((r, c + pad), float("nan"), dtype=torch.float64, device="cuda")
+            view = base[:, :c]
+        view.copy_(torch.from_numpy(x))
+        return view
+
+    A = dev(opa.T.copy() if trans[0] == "T" else opa, la, 3)
+    B = dev(opb.T.copy() if trans[1] == "T" else opb, lb, 5)
+    C = dev(c0, lc, 2)
+    mdg.gemm2d(A, B, C, 1.5, -0.5, trans[0], trans[1])
+    assert oracle_dgemm_dense(opa, opb, c0, 1.5, -0.5)  # c0 := the oracle's result
+    assert same_bits(C.cpu().numpy(), c0)

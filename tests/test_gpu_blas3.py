@@ -7,8 +7,9 @@ the diagonal, so the solution is X0). Uniform data: syrk and trmm within 1e-13 D
 D = |alpha| |op(A)| |op(B)| (+ |beta| |C0|), as for the GEMM; trsm by its residual
 alpha B - op(A) X (or alpha B - X op(A)) evaluated in doubled precision by the oracle, within
 1e-13 (|op(A)| |X| + |alpha| |B|), and within 1e-12 max|X| of the oracle's substitution.
-Orders cross the 64-row leaf of the triangular recursion several times and end in ragged
-blocks; the triangle not named by uplo, a unit diagonal and all padding hold NaN.
+Orders cross the 64-row leaf of the triangular recursion several times (up to four levels of
+halving) and end in ragged blocks; the triangle not named by uplo, a unit diagonal and all padding
+hold NaN.
 """
 import itertools
 
@@ -22,7 +23,7 @@ from gpu_util import TOL, sample_indices, to_dev
 pytestmark = pytest.mark.gpu
 
 COMBOS = list(itertools.product("LR", "LU", "NT", "NU"))
-TRI_SHAPES = [(1, 1), (7, 5), (64, 64), (65, 33), (130, 70), (200, 300)]
+TRI_SHAPES = [(1, 1), (7, 5), (64, 64), (65, 33), (130, 70), (200, 300), (700, 90), (90, 1100)]
 SYRK_SHAPES = [(1, 1), (5, 3), (64, 16), (65, 17), (130, 70), (257, 129), (300, 513)]
 
 

@@ -163,3 +163,27 @@ def test_wave_class_cannot_mix_with_workgroup_classes():
     n0 = mdg.mdg_grouped_plan_bytes(descs, [2] * 10)
     tiles = sum(-(-d.m // 32) * -(-d.n // 32) for d in descs)
     assert n0 == 64 + 80 + 10 * 136 + 16 * tiles  # 136-byte descriptors
+
+
+def test_tuner_times_each_candidate_with_its_own_tile_kind(monkeypatch):
+    """The tuner builds each candidate's plan with that candidate's tile classes (wave tiles for a
+    wave policy, the threshold's workgroup classes otherwise); the plan constructor is replaced
+    by a recorder, so nothing reaches the GPU."""
+    from paper_1609_00076_amd import tuner
+    seen = []
+
+    class Stop(Exception):
+        pass
+
+    def fake_plan(gemms, classes, schedule):
+        seen.append((list(classes), schedule))
+        raise Stop
+
+    monkeypatch.setattr(tuner, "GroupedPlan", fake_plan)
+    gemms = [dict(m=m, n=n) for m, n in ((30, 100), (100, 100), (50, 39))]
+    for pol, want in (({"tile": "wave", "threshold": 0, "schedule": 1, "grid": 512}, [2, 2, 2]),
+                      ({"tile": "block", "threshold": 40, "schedule": 0, "grid": 512}, [1, 0, 1]),
+                      ({"tile": "block", "threshold": 0, "schedule": 1, "grid": 256}, [0, 0, 0])):
+        with pytest.raises(Stop):
+            tuner.time_policy(gemms, pol)
+        assert seen[-1] == (want, pol["schedule"])

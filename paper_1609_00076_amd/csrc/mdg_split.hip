@@ -778,26 +778,33 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* X, int64
         residues16(q, c_moduli[l]);
 }
 
-// Step 3: the modular products. Workgroup: one modulus l and one 256 x 128 tile of C, 8 waves
-// (4 x 2) of 64 x 64, each 2 x 2 blocks of v_mfma_i32_32x32x32_i8 (lane layout as in
-// split32_tile). The 32-deep k-steps go through a ring of 3 LDS stages of 12 chunks (8 of A, 4 of
-// B), filled by direct loads two steps ahead. At the end each lane reduces its accumulators
-// modulo m_l and writes them, four columns to a 32-bit word, to R_l[(j/4) m + i] (R_l holds
-// m * ceil(n/4) words). Workgroups are ordered modulus-major, so each XCD works on one or two
-// moduli at a time and their residue slices stay in its L2 and the Infinity Cache.
-constexpr int kCrtMT = 256, kCrtNT = 128, kCrtStages = 3;
-constexpr int kCrtACh = kCrtMT / 32, kCrtBCh = kCrtNT / 32;
-// KH: 32-deep k-panels per stage (a stage holds KH panels of A's 8 chunks and B's 4).
-template <int KH>
+// Step 3: the modular products. Workgroup: one modulus l and one MT x NT tile of C, 8 waves of
+// WM x WN, each (WM/32) x (WN/32) blocks of v_mfma_i32_32x32x32_i8 (lane layout as in
+// split32_tile). The k-steps (KH 32-deep panels each) go through a ring of 3 LDS stages filled by
+// direct loads two steps ahead. At the end each lane reduces its accumulators modulo m_l and
+// writes them, four columns to a 32-bit word, to R_l[(j/4) m + i] (R_l holds m * ceil(n/4)
+// words). Workgroups are ordered modulus-major, so each XCD works on one or two moduli at a time
+// and their residue slices stay in its L2 and the Infinity Cache.
+constexpr int kCrtStages = 3;
+template <int MT_, int NT_, int WM_, int WN_, int KH_>
 struct CrtCfg {
+  static constexpr int MT = MT_, NT = NT_, WM = WM_, WN = WN_, KH = KH_;
+  static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
+  static_assert(WAVES_M * WAVES_N == kThreads / 64, "8 waves");
+  static constexpr int BI = WM / 32, BJ = WN / 32;       // MFMA blocks per wave
+  static constexpr int ACH = MT / 32, BCH = NT / 32;     // 1 KiB chunks per 32-deep panel
   static constexpr int KSTEP = 32 * KH;
-  static constexpr int CH = KH * (kCrtACh + kCrtBCh);  // chunks per stage
-  static constexpr int LOADS = (CH + 7) / 8;           // direct loads per wave per stage
+  static constexpr int CH = KH * (ACH + BCH);            // chunks per stage
+  static constexpr int LOADS = (CH + 7) / 8;             // direct loads per wave per stage
   static constexpr int STAGE = CH * kChunk;
   static constexpr int LDS = kCrtStages * STAGE + kChunk;  // + a trash chunk for idle loads
   static_assert((kCrtStages - 1) * LOADS <= 63, "vmcnt range");
 };
-constexpr int kCrtKH = 2;  // the configuration the library runs
+// The configuration the library runs: 256 x 128 tiles, 8 waves of 64 x 64, 64-deep steps. Larger
+// wave tiles, which read fewer LDS bytes per MFMA (256 x 256 with waves of 128 x 64 or 64 x 128,
+// 512 x 128 with 128 x 64), and 128 x 256 tiles all measured within 4% of it at 8192^3: the
+// products run at the power limit of the INT8 matrix cores, not at an LDS or issue limit.
+using CrtRun = CrtCfg<256, 128, 64, 64, 2>;
 
 struct CrtArgs {
   int64_t m, n, kp;
@@ -808,13 +815,13 @@ struct CrtArgs {
   int fold_steps;    // k-steps after which the accumulators are reduced modulo m_l
 };
 
-template <int KH>
+template <class K>
 __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int tiles_n,
                                               int8_t* lds) {
-  using K = CrtCfg<KH>;
+  constexpr int KH = K::KH;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wave_m = wave & 3, wave_n = wave >> 2;
+  const int wave_m = wave % K::WAVES_M, wave_n = wave / K::WAVES_M;
 
   // XCD-aware order over (modulus, tile): each XCD a contiguous run, modulus-major, tiles in
   // column groups of 4 tile-rows. The host rounds the grid up to a multiple of 8.
@@ -831,7 +838,7 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   const int rem = t - grp * per_group;
   const int tm = __builtin_amdgcn_readfirstlane(first_m + rem % gsize);
   const int tn = __builtin_amdgcn_readfirstlane(rem / gsize);
-  const int64_t row0 = (int64_t)tm * kCrtMT, col0 = (int64_t)tn * kCrtNT;
+  const int64_t row0 = (int64_t)tm * K::MT, col0 = (int64_t)tn * K::NT;
   const int m_l = c_moduli[l];
 
   const int64_t rpa = round128(g.m), rpb = round128(g.n);
@@ -840,18 +847,20 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   const int8_t* b_base = g.Bs + l * slice_b;
   const int nsteps = (int)(g.kp / K::KSTEP);  // >= 1: kp is a positive multiple of 64
 
-  // Direct load u of wave w moves chunk c = 8u + w of the stage: chunk c < 8 KH is rows
-  // 32 (c % 8).. of A in panel c / 8 of the step, c < 12 KH rows 32 (c' % 4).. of B in panel
-  // c' / 4 (c' = c - 8 KH), the rest idle (an empty buffer into the trash chunk).
+  // Direct load u of wave w moves chunk c = 8u + w of the stage: chunk c < ACH KH is rows
+  // 32 (c % ACH).. of A in panel c / ACH of the step, c < CH rows 32 (c' % BCH).. of B in panel
+  // c' / BCH (c' = c - ACH KH), the rest idle (an empty buffer into the trash chunk). Rows past
+  // the rounded row count read the next panel's rows (still inside the slice) or, past the slice,
+  // zeros: either way they feed only rows or columns of C that are not stored.
   uint32_t voff[K::LOADS];
 #pragma unroll
   for (int u = 0; u < K::LOADS; ++u) {
     const int c = 8 * u + wave;
     int64_t o = 0;
-    if (c < kCrtACh * KH) o = (c / kCrtACh) * rpa * 32 + (row0 + 32 * (c % kCrtACh)) * 32;
+    if (c < K::ACH * KH) o = (c / K::ACH) * rpa * 32 + (row0 + 32 * (c % K::ACH)) * 32;
     else if (c < K::CH) {
-      const int cb = c - kCrtACh * KH;
-      o = (cb / kCrtBCh) * rpb * 32 + (col0 + 32 * (cb % kCrtBCh)) * 32;
+      const int cb = c - K::ACH * KH;
+      o = (cb / K::BCH) * rpb * 32 + (col0 + 32 * (cb % K::BCH)) * 32;
     }
     voff[u] = (uint32_t)o + 16u * (uint32_t)lane;
   }
@@ -860,7 +869,7 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
 #pragma unroll
     for (int u = 0; u < K::LOADS; ++u) {
       const int c = 8 * u + wave;
-      const bool is_a = c < kCrtACh * KH, is_b = !is_a && c < K::CH;
+      const bool is_a = c < K::ACH * KH, is_b = !is_a && c < K::CH;
       const int8_t* base = is_b ? b_base : a_base;
       const int64_t bytes = is_a ? slice_a : is_b ? slice_b : 0;
       const uint32_t soff = is_a ? (uint32_t)ks * (uint32_t)(rpa * K::KSTEP)
@@ -872,25 +881,27 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   };
 
   const int frag = 16 * row_slot(lane & 31, lane >> 5);
-  const int a_frag = 2 * wave_m * kChunk + frag;                    // + (bi + 8 h) KiB
-  const int b_frag = (kCrtACh * KH + 2 * wave_n) * kChunk + frag;   // + (bj + 4 h) KiB
-  v4i af[KH][2], bf[KH][2];
+  const int a_frag = K::BI * wave_m * kChunk + frag;                   // + (bi + ACH h) KiB
+  const int b_frag = (K::ACH * KH + K::BJ * wave_n) * kChunk + frag;  // + (bj + BCH h) KiB
+  v4i af[KH][K::BI], bf[KH][K::BJ];
   auto read = [&](int ks) __attribute__((always_inline)) {
     const int8_t* st = lds + (ks % kCrtStages) * K::STAGE;
 #pragma unroll
-    for (int h = 0; h < KH; ++h)
+    for (int h = 0; h < KH; ++h) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        af[h][b] = *reinterpret_cast<const v4i*>(st + a_frag + (b + kCrtACh * h) * kChunk);
-        bf[h][b] = *reinterpret_cast<const v4i*>(st + b_frag + (b + kCrtBCh * h) * kChunk);
-      }
+      for (int b = 0; b < K::BI; ++b)
+        af[h][b] = *reinterpret_cast<const v4i*>(st + a_frag + (b + K::ACH * h) * kChunk);
+#pragma unroll
+      for (int b = 0; b < K::BJ; ++b)
+        bf[h][b] = *reinterpret_cast<const v4i*>(st + b_frag + (b + K::BCH * h) * kChunk);
+    }
   };
 
-  v16i acc[2][2];
+  v16i acc[K::BI][K::BJ];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < K::BI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < K::BJ; ++bj)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[bi][bj][r] = 0;
   // acc := acc mod m_l (in [0, m_l)), exact for |acc| < 2^31 and m_l >= 128: the float quotient
@@ -899,9 +910,9 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   const float inv = 1.0f / (float)m_l;
   auto reduce = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < K::BI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < K::BJ; ++bj)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int vv = acc[bi][bj][r];
@@ -919,9 +930,9 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
 #pragma unroll
     for (int h = 0; h < KH; ++h)
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < K::BI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < K::BJ; ++bj)
           acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[h][bj], af[h][bi], acc[bi][bj],
                                                               0, 0, 0);
     __builtin_amdgcn_sched_barrier(0);
@@ -961,14 +972,14 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   const int64_t words_n = (g.n + 3) / 4;
   uint32_t* R = g.R + (int64_t)l * g.m * words_n;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
-    const int64_t i = row0 + 64 * wave_m + 32 * bi + (lane & 31);
+  for (int bi = 0; bi < K::BI; ++bi) {
+    const int64_t i = row0 + K::WM * wave_m + 32 * bi + (lane & 31);
     if (i >= g.m) continue;
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < K::BJ; ++bj)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t j = col0 + 64 * wave_n + 32 * bj + 8 * q + 4 * (lane >> 5);
+        const int64_t j = col0 + K::WN * wave_n + 32 * bj + 8 * q + 4 * (lane >> 5);
         if (j >= g.n) continue;
         const uint32_t word = (uint32_t)acc[bi][bj][4 * q] |
                               ((uint32_t)acc[bi][bj][4 * q + 1] << 8) |
@@ -979,11 +990,11 @@ __device__ __forceinline__ void crt_gemm_tile(const CrtArgs& g, int tiles_m, int
   }
 }
 
-template <int KH>
+template <class K>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
 crt_gemm_kernel(CrtArgs g, int tiles_m, int tiles_n) {
-  __shared__ __attribute__((aligned(1024))) int8_t lds[CrtCfg<KH>::LDS];
-  crt_gemm_tile<KH>(g, tiles_m, tiles_n, lds);
+  __shared__ __attribute__((aligned(1024))) int8_t lds[K::LDS];
+  crt_gemm_tile<K>(g, tiles_m, tiles_n, lds);
 }
 
 // Step 4 and 5 constants, computed on the host for the call's modulus count. Step 4 works in
@@ -1419,7 +1430,7 @@ int crt_size_check(int64_t m, int64_t n, int nmod, const CrtLayout& L) {
   // per-modulus slices are addressed by 32-bit offsets from a 64-bit base
   if (round128(m) * L.kp > (int64_t)0xFFFFFFFF - 4096 || round128(n) * L.kp > (int64_t)0xFFFFFFFF - 4096)
     return MDG_ERR_SIZE;
-  const int64_t tiles = ((m + kCrtMT - 1) / kCrtMT) * ((n + kCrtNT - 1) / kCrtNT);
+  const int64_t tiles = ((m + CrtRun::MT - 1) / CrtRun::MT) * ((n + CrtRun::NT - 1) / CrtRun::NT);
   if (tiles * nmod > (int64_t)INT32_MAX / 256 || (n + 3) / 4 > 65535 || (m + 255) / 256 > INT32_MAX)
     return MDG_ERR_SIZE;
   return MDG_SUCCESS;
@@ -1442,12 +1453,12 @@ int crt_run(char transa, char transb, int64_t m, int64_t n, int64_t k, double al
   st = launch_crt_residues(is_notrans(transb), B, ldb, n, k, L.kp, nmod, bits, bs, eb, s);
   if (st) return st;
   // INT32 headroom: |a_l b_l| <= 128^2 per term, KSTEP terms per step, plus a residue < 256
-  const int fold = (int)(((int64_t)INT32_MAX - 256) / ((int64_t)CrtCfg<kCrtKH>::KSTEP * 128 * 128));
+  const int fold = (int)(((int64_t)INT32_MAX - 256) / ((int64_t)CrtRun::KSTEP * 128 * 128));
   CrtArgs g{m, n, L.kp, as, bs, R, nmod, fold};
-  int tm = (int)((m + kCrtMT - 1) / kCrtMT), tn = (int)((n + kCrtNT - 1) / kCrtNT);
+  int tm = (int)((m + CrtRun::MT - 1) / CrtRun::MT), tn = (int)((n + CrtRun::NT - 1) / CrtRun::NT);
   {
     void* argv[] = {&g, &tm, &tn};
-    st = launch(reinterpret_cast<const void*>(&crt_gemm_kernel<kCrtKH>),
+    st = launch(reinterpret_cast<const void*>(&crt_gemm_kernel<CrtRun>),
                 dim3((unsigned)(((int64_t)tm * tn * nmod + 7) / 8 * 8)), dim3(kThreads), s, argv);
     if (st) return st;
   }

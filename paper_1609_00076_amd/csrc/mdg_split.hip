@@ -1028,22 +1028,29 @@ __global__ void __launch_bounds__(256) crt_combine_kernel(CombineArgs a, CrtCons
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t w = blockIdx.y;
   if (i >= a.m) return;
-  uint32_t res[kMaxModuli];
-  for (int l = 0; l < k.nmod; ++l) res[l] = a.R[((int64_t)l * words_n + w) * a.m + i];
+  // S_c = sum_l r_l W_l for the four columns at once, so each modulus' word of residues and its
+  // limbs of W_l (uniform, read through the scalar unit) are loaded once: 24-bit products, at
+  // most 24 of them per limb.
+  uint32_t sc[4][L];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int t = 0; t < L; ++t) sc[c][t] = 0;
+  for (int l = 0; l < k.nmod; ++l) {
+    const uint32_t word = a.R[((int64_t)l * words_n + w) * a.m + i];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t r = (word >> (8 * c)) & 0xFFu;
+#pragma unroll
+      for (int t = 0; t < L; ++t) sc[c][t] += __umul24(r, (uint32_t)k.W[l][t]);
+    }
+  }
   const int enc_i = a.ea[i];
-#pragma unroll 1
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int64_t j = 4 * w + c;
     if (j >= a.n) break;
-    // S = sum_l r_l W_l: 24-bit products, at most 24 of them per limb
-    uint32_t s[L];
-#pragma unroll
-    for (int t = 0; t < L; ++t) s[t] = 0;
-    for (int l = 0; l < k.nmod; ++l) {
-      const uint32_t r = (res[l] >> (8 * c)) & 0xFFu;
-#pragma unroll
-      for (int t = 0; t < L; ++t) s[t] += __umul24(r, (uint32_t)k.W[l][t]);
-    }
+    uint32_t (&s)[L] = sc[c];
     uint32_t carry = 0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {

@@ -690,11 +690,23 @@ __device__ __forceinline__ int mod_small(int v, int m, float inv) {
   return r;
 }
 
-// Residues of 16 scaled entries (integers of at most 72 bits held in binary64) for one modulus,
-// as 16 int8 bytes in the symmetric range. |a| = c 2^t with c < 2^53 an integer (t > 0 only past
-// 53 bits, where the low bits of a are zero), so |a| mod m = (c mod m)(2^t mod m) mod m; c mod m is
-// c - q m with q = floor(c / m) from the binary64 quotient, which is within one of the truth, and
-// the remainder c - q m is exact (one fused multiply-add of a result below 2m in magnitude).
+// 1/m_l rounded to binary64 and binary32, for the quotients below.
+__constant__ double c_inv[kMaxModuli] = {
+    1.0 / 256, 1.0 / 255, 1.0 / 253, 1.0 / 251, 1.0 / 247, 1.0 / 241, 1.0 / 239, 1.0 / 233,
+    1.0 / 229, 1.0 / 227, 1.0 / 223, 1.0 / 211, 1.0 / 199, 1.0 / 197, 1.0 / 193, 1.0 / 191,
+    1.0 / 181, 1.0 / 179, 1.0 / 173, 1.0 / 167, 1.0 / 163, 1.0 / 157, 1.0 / 151, 1.0 / 149};
+__constant__ float c_finv[kMaxModuli] = {
+    1.0f / 256, 1.0f / 255, 1.0f / 253, 1.0f / 251, 1.0f / 247, 1.0f / 241, 1.0f / 239, 1.0f / 233,
+    1.0f / 229, 1.0f / 227, 1.0f / 223, 1.0f / 211, 1.0f / 199, 1.0f / 197, 1.0f / 193, 1.0f / 191,
+    1.0f / 181, 1.0f / 179, 1.0f / 173, 1.0f / 167, 1.0f / 163, 1.0f / 157, 1.0f / 151, 1.0f / 149};
+
+// Symmetric residues of 16 scaled entries (integers of at most 72 bits held in binary64) for
+// modulus l, as 16 int8 bytes in [-(m/2), m - m/2 - 1]. |a| = c 2^t with c < 2^53 an integer (t > 0
+// only past 53 bits, where the low bits of a are zero). d = c - rint(c / m) m is formed exactly by
+// one fused multiply-add (it is below 2m in magnitude) with the quotient from binary64, which is
+// the nearest integer to c / m or next to it; so d is within one m of the symmetric residue of c,
+// and after the sign of a one correction either way gives the residue. Past 53 bits, d is first
+// brought into [0, m) and multiplied by 2^t mod m.
 struct Parts16 {
   double c[16];
   int t[16];
@@ -714,24 +726,27 @@ __device__ __forceinline__ void split_parts(const double (&a)[16], Parts16& q) {
   }
 }
 
-__device__ __forceinline__ v4i residues16(const Parts16& q, int m) {
-  const double dm = (double)m, inv = 1.0 / dm;
-  const float finv = 1.0f / (float)m;
-  const int half = m - m / 2;
+__device__ __forceinline__ v4i residues16(const Parts16& q, int l) {
+  const int m = c_moduli[l];
+  const double dm = (double)m, inv = c_inv[l];
+  const float finv = c_finv[l];
+  const int lo = -(m / 2), hi = m - m / 2 - 1;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const double c = q.c[e];
-    double r = fma(-floor(c * inv), dm, c);
-    r += (r < 0.0) ? dm : 0.0;
-    r -= (r >= dm) ? dm : 0.0;
-    int x = (int)r;
+    int x = (int)fma(-rint(c * inv), dm, c);
     if (q.t[e]) {  // times 2^t mod m, t < 20: (2^t mod m) by one shift and reduction
+      x += (x < 0) ? m : 0;
+      x += (x < 0) ? m : 0;
+      x -= (x >= m) ? m : 0;
+      x -= (x >= m) ? m : 0;
       const int p2 = mod_small(1 << q.t[e], m, finv);
       x = mod_small(x * p2, m, finv);
     }
-    if (q.neg[e] && x != 0) x = m - x;
-    if (x >= half) x -= m;
+    if (q.neg[e]) x = -x;
+    x += (x < lo) ? m : 0;
+    x -= (x > hi) ? m : 0;
     w[e / 4] |= ((uint32_t)x & 0xFFu) << (8 * (e % 4));
   }
   return (v4i){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
@@ -775,7 +790,7 @@ __global__ void __launch_bounds__(256) crt_residue_kernel(const double* X, int64
   split_parts(a, q);
   for (int l = 0; l < nmod; ++l)
     *reinterpret_cast<v4i*>(out + slice_offset(l, row0 + r, p0 + q0, rp, kp)) =
-        residues16(q, c_moduli[l]);
+        residues16(q, l);
 }
 
 // Step 3: the modular products. Workgroup: one modulus l and one MT x NT tile of C, 8 waves of

@@ -76,34 +76,49 @@ __device__ __forceinline__ void leaf_body(const LeafArgs& a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
 
-  // Stage M with the stored block's contiguous index running fastest across the threads; the
-  // loop is unrolled so that a thread's loads are in flight together.
+  // The vectors' entries, lane i holding entry i of each, loaded from clamped addresses and
+  // issued first so that their latency overlaps the staging of M.
+  const int64_t v0 = ((int64_t)blockIdx.x * kLeafWaves + wave) * kLeafVecsPerWave;
+  const bool row_ok = lane < a.nb;
+  double y[kLeafVecsPerWave];
 #pragma unroll
-  for (int r = 0; r < kLeaf * kLeaf / (kLeafWaves * 64); ++r) {
+  for (int q = 0; q < kLeafVecsPerWave; ++q) {
+    const int64_t v = v0 + q < a.nvec ? v0 + q : a.nvec - 1;
+    y[q] = a.Y[v * a.vs + (int64_t)(row_ok ? lane : a.nb - 1) * a.es];
+  }
+
+  // Stage M with the stored block's contiguous index running fastest across the threads. Every
+  // load is issued, from an address clamped into the nb x nb block, so that a thread's 16 loads
+  // are in flight together (loads under a condition went out one at a time, each waited for);
+  // entries outside the triangle, on a unit diagonal or beyond nb are then replaced, so their
+  // values never reach the result.
+  constexpr int kStage = kLeaf * kLeaf / (kLeafWaves * 64);
+  double mv[kStage];
+#pragma unroll
+  for (int r = 0; r < kStage; ++r) {
     const int e = tid + r * kLeafWaves * 64;
     const int outer = e / kLeaf, inner = e % kLeaf;
-    const int i = a.mt ? outer : inner;  // M row
-    const int p = a.mt ? inner : outer;  // M column
+    const int i = min(a.mt ? outer : inner, a.nb - 1);  // M row (clamped)
+    const int p = min(a.mt ? inner : outer, a.nb - 1);  // M column (clamped)
+    mv[r] = a.mt ? a.A[(int64_t)i * a.lda + p] : a.A[(int64_t)p * a.lda + i];
+  }
+#pragma unroll
+  for (int r = 0; r < kStage; ++r) {
+    const int e = tid + r * kLeafWaves * 64;
+    const int outer = e / kLeaf, inner = e % kLeaf;
+    const int i = a.mt ? outer : inner, p = a.mt ? inner : outer;
     const bool in_tri = LOWER ? p <= i : p >= i;
-    double x = (i == p) ? 1.0 : 0.0;
-    if (i < a.nb && p < a.nb && in_tri && !(i == p && a.unit))
-      x = a.mt ? a.A[(int64_t)i * a.lda + p] : a.A[(int64_t)p * a.lda + i];
-    Ms[i][p] = x;
+    const bool keep = i < a.nb && p < a.nb && in_tri && !(i == p && a.unit);
+    Ms[i][p] = keep ? mv[r] : ((i == p) ? 1.0 : 0.0);
   }
   __syncthreads();
 
   double mrow[kLeaf];
 #pragma unroll
   for (int c = 0; c < kLeaf; ++c) mrow[c] = Ms[lane][c];
-
-  const int64_t v0 = ((int64_t)blockIdx.x * kLeafWaves + wave) * kLeafVecsPerWave;
-  const bool row_ok = lane < a.nb;
-  double y[kLeafVecsPerWave];
 #pragma unroll
-  for (int q = 0; q < kLeafVecsPerWave; ++q) {
-    const int64_t v = v0 + q;
-    y[q] = (v < a.nvec && row_ok) ? a.Y[v * a.vs + (int64_t)lane * a.es] : 0.0;
-  }
+  for (int q = 0; q < kLeafVecsPerWave; ++q) y[q] = (v0 + q < a.nvec && row_ok) ? y[q] : 0.0;
+
   const double alpha = a.alpha;
 
   if (SOLVE) {

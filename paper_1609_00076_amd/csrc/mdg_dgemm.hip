@@ -50,8 +50,7 @@ struct GemmArgs {
 // ------------------------------------------------------------------------------------------------
 // Tile configuration. MT x NT macro-tile per workgroup, KT-deep k-panels, WM x WN per wave.
 // ------------------------------------------------------------------------------------------------
-template <int MT_, int NT_, int KT_, int WM_, int WN_, int MIN_WAVES_PER_EU_, int PAD_MODE_ = 1,
-          bool PREFETCH_C_ = false>
+template <int MT_, int NT_, int KT_, int WM_, int WN_, int MIN_WAVES_PER_EU_, int PAD_MODE_ = 1>
 struct Cfg {
   static constexpr int MT = MT_, NT = NT_, KT = KT_, WM = WM_, WN = WN_;
   static constexpr int MIN_WAVES_PER_EU = MIN_WAVES_PER_EU_;  // occupancy target per SIMD
@@ -59,9 +58,6 @@ struct Cfg {
   // for an operand whose global rows run along m or n, which makes the fragment reads of
   // consecutive k-rows fall in disjoint bank halves.
   static constexpr int PAD_MODE = PAD_MODE_;
-  // Load the old C of this thread's outputs before the k-loop (for short k, where the epilogue's
-  // HBM traffic would otherwise start only after the arithmetic).
-  static constexpr bool PREFETCH_C = PREFETCH_C_;
   static constexpr int WAVES_M = MT / WM, WAVES_N = NT / WN;
   static constexpr int WAVES = WAVES_M * WAVES_N;
   static constexpr int THREADS = WAVES * 64;
@@ -222,23 +218,26 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, dou
   const double alpha = g.alpha, beta = g.beta;
 
   // Old C of this lane's outputs in column block bj (BM x 4 values), all loads issued together.
+  // The old C of one column block of this lane's outputs. Every load is issued, from an address
+  // clamped into C, and the entries outside C are replaced afterwards: under conditions the loads
+  // (and the stores after them) were left to the compiler's most cautious counting, which waited
+  // for every store of the epilogue to complete before the next one went out. The explicit wait
+  // leaves no load outstanding when the stores start.
   auto load_c_block = [&](int bj, double (&dst)[C::BM][4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t dj = 16 * bj + 4 * r;
-      const bool col_ok = j0 + dj < g.n;
+      const int64_t j = min(j0 + 16 * bj + 4 * r, g.n - 1);
 #pragma unroll
-      for (int bi = 0; bi < C::BM; ++bi)
-        dst[bi][r] = (col_ok && i0 + 16 * bi < g.m) ? cbase[dj * g.ldc + 16 * bi] : 0.0;
+      for (int bi = 0; bi < C::BM; ++bi) dst[bi][r] = g.C[j * g.ldc + min(i0 + 16 * bi, g.m - 1)];
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool col_ok = j0 + 16 * bj + 4 * r < g.n;
+#pragma unroll
+      for (int bi = 0; bi < C::BM; ++bi) dst[bi][r] = (col_ok && i0 + 16 * bi < g.m) ? dst[bi][r] : 0.0;
     }
   };
-  // With PREFETCH_C the whole tile's old C is loaded before the k-loop, so that its HBM reads
-  // overlap the arithmetic; otherwise the epilogue loads it one column block at a time.
-  double c0[C::PREFETCH_C ? C::BN : 1][C::BM][4];
-  if (C::PREFETCH_C && beta != 0.0) {
-#pragma unroll
-    for (int bj = 0; bj < C::BN; ++bj) load_c_block(bj, c0[C::PREFETCH_C ? bj : 0]);
-  }
 
   PanelMap<C::A_PER_THREAD> ma;
   PanelMap<C::B_PER_THREAD> mb;
@@ -314,14 +313,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
   for (int bj = 0; bj < C::BN; ++bj) {
     double cb[C::BM][4];
-    if (C::PREFETCH_C) {
-#pragma unroll
-      for (int bi = 0; bi < C::BM; ++bi)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cb[bi][r] = c0[C::PREFETCH_C ? bj : 0][bi][r];
-    } else if (beta != 0.0) {
-      load_c_block(bj, cb);
-    }
+    if (beta != 0.0) load_c_block(bj, cb);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t dj = 16 * bj + 4 * r;
@@ -918,15 +910,30 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     if (bj2 / kHalf != grp) continue;
     double cb[R::BM][4];
     if (beta != 0.0) {
+      // Every load issued, from an address inside C (and inside the triangle when TRI: the
+      // diagonal entry of the column stands in for entries outside it); entries outside are
+      // replaced after an explicit wait, so that no load is outstanding when the stores start
+      // (loads under conditions left the compiler waiting for each store in turn).
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t j = col_of(bj2, r);
-        const bool col_ok = j < g.n;
+        const int64_t j = min(col_of(bj2, r), g.n - 1);
 #pragma unroll
         for (int bi = 0; bi < R::BM; ++bi) {
           const int64_t i = row_of(bi);
           const bool tri_ok = TRI == 0 || (TRI == 1 ? i >= j : i <= j);
-          cb[bi][r] = (col_ok && i < g.m && tri_ok) ? g.C[j * g.ldc + i] : 0.0;
+          const int64_t ic = (TRI == 0 || tri_ok) ? min(i, g.m - 1) : j;
+          cb[bi][r] = g.C[j * g.ldc + ic];
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = col_of(bj2, r);
+#pragma unroll
+        for (int bi = 0; bi < R::BM; ++bi) {
+          const int64_t i = row_of(bi);
+          const bool tri_ok = TRI == 0 || (TRI == 1 ? i >= j : i <= j);
+          cb[bi][r] = (j < g.n && i < g.m && tri_ok) ? cb[bi][r] : 0.0;
         }
       }
     }

@@ -149,6 +149,34 @@ def traffic_from(dirs, copy_bytes, mdg):
               f"{meas / alg:.1f} |")
 
 
+def blas3_traffic_from(dirs, copy_bytes, n=8192):
+    """Write BLAS3_TRAFFIC_FILE from four rocprofv3 --pmc runs as in traffic_from, the first two
+    of `bench.py --workload blas3 --steps 1 --warmup 0 --cpu-budget 0`: the dsyrk launch's bytes."""
+    f_dir, w_dir, cf_dir, cw_dir = dirs
+    def scale(run_dir, counter):
+        vals = [v for _, (name, v) in sorted(read_counter(run_dir, counter).items())]
+        return copy_bytes / (sorted(vals[-3:])[1] * 1024.0)
+    fs, ws = scale(cf_dir, "FETCH_SIZE"), scale(cw_dir, "WRITE_SIZE")
+    got = {}
+    for counter, d, sc in (("FETCH_SIZE", f_dir, fs), ("WRITE_SIZE", w_dir, ws)):
+        vals = [v for _, (name, v) in sorted(read_counter(d, counter).items())
+                if "dsyrk_ring_kernel" in name]
+        if not vals:
+            raise SystemExit(f"{counter}: no dsyrk dispatch in {d}")
+        got[counter] = (sum(vals) / len(vals) * 1024.0 * sc, len(vals))
+    alg = 8.0 * (n * n + n * (n + 1))  # A read once, the triangle of C read and written
+    out = {"source_sha": source_hash(), "n": n,
+           "dsyrk_bytes_per_launch": got["FETCH_SIZE"][0] + got["WRITE_SIZE"][0],
+           "fetch_bytes": got["FETCH_SIZE"][0], "write_bytes": got["WRITE_SIZE"][0],
+           "launches": [got["FETCH_SIZE"][1], got["WRITE_SIZE"][1]],
+           "fetch_scale": fs, "write_scale": ws, "algorithmic_bytes": alg,
+           "note": f"dsyrk L N n=k={n} launch: FETCH_SIZE + WRITE_SIZE (KiB x 1024) times the "
+                   "factors that map each counter's reading of a device copy to the bytes it moves"}
+    with open(BLAS3_TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def out_workload(probs):
     return sorted({f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}" for p in probs})
 
@@ -910,7 +938,10 @@ def main():
     import paper_1609_00076_amd as mdg
     mdg.load()
     if args.traffic_from:
-        traffic_from(args.traffic_from.split(","), args.copy_calibration or (1 << 30), mdg)
+        if args.workload == "blas3":
+            blas3_traffic_from(args.traffic_from.split(","), args.copy_calibration or (1 << 30))
+        else:
+            traffic_from(args.traffic_from.split(","), args.copy_calibration or (1 << 30), mdg)
         return
     if not torch.cuda.is_available():
         print("bench.py: no HIP device visible", file=sys.stderr)

@@ -1040,6 +1040,31 @@ def main():
         med = sorted(times)[len(times) // 2]
         breakdown[name] = round(2.0 * m * n * k / (med * 1e-3) / 1e12, 2)
 
+    # The skinny GEMM against the reachable streaming rate: the library's own C := beta*C kernel
+    # (alpha = 0 takes it; a grid-stride read and write of C) on the same C, timed the same way.
+    skinny = None
+    sk = [p for p in probs if p["k"] == SKINNY[2]]
+    if sk:
+        p0 = sk[0]
+        m, n = p0["m"], p0["n"]
+        def st():
+            if mdg.mdg_dgemm("N", "N", m, n, p0["k"], 0.0, None, m, None, p0["k"], 0.5, p0["C"],
+                             p0["ldc"]):
+                raise RuntimeError("C := beta*C refused")
+        stream_ms = events_ms(torch, st, 20, 3)
+        stream_tbs = 2.0 * 8.0 * m * n / (stream_ms * 1e-3) / 1e12
+        gemm_tbs = {}
+        for p in sk:
+            name = f"{p['transa']}{p['transb']} {p['m']}x{p['n']}x{p['k']}"
+            med = sorted(per_problem[name])[len(per_problem[name]) // 2]
+            gemm_tbs[p["transa"] + p["transb"]] = round(hbm_bytes(p) / (med * 1e-3) / 1e12, 3)
+        skinny = {"shape": f"{m}x{n}x{p0['k']}",
+                  "stream_kernel": "C := beta*C (the library's alpha = 0 path), same C",
+                  "stream_TBps": round(stream_tbs, 3), "gemm_TBps": gemm_tbs,
+                  "frac_of_stream": {t: round(v / stream_tbs, 3) for t, v in gemm_tbs.items()},
+                  "frac_of_hbm_peak": {t: round(v / (PEAK_HBM_GBS / 1e3), 3)
+                                       for t, v in gemm_tbs.items()}}
+
     cpu = None
     if args.cpu_budget > 0:
         log("[bench] timing the CPU oracle baseline")
@@ -1100,6 +1125,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "per_problem_tflops": breakdown,
+        "skinny_vs_stream": skinny,
     }
     if workloads is not None:
         out["workloads"] = workloads

@@ -89,12 +89,29 @@ int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, in
                  double beta, double *C, int64_t ldc, void *stream);
 
 /*
- * The variant mdg_dgemm would launch for these arguments, or -1 when it would
- * launch no GEMM kernel (quick return, or the alpha == 0 / k == 0 scaling
- * path). Pure host function: no HIP call, no pointer dereference.
+ * The tiled variant mdg_dgemm would launch for these arguments, or -1 when it
+ * would launch none (quick return, the alpha == 0 / k == 0 scaling path, or a
+ * C with at most 16 rows or columns computed by the thin kernel alone). The
+ * variant may cover only the leading block of C: see mdg_dgemm_plan. Pure
+ * host function: no HIP call, no pointer dereference.
  */
 int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k,
                        double alpha, double beta);
+
+/*
+ * How mdg_dgemm (automatic variant) splits a product with m, n, k >= 1 (paper,
+ * section 2.4: the fringes left when m, n are not multiples of the block
+ * sizes). *variant (or -1: none) computes rows [0, *m_main) and columns
+ * [0, *n_main) of C with its tiles; one launch of the thin kernel computes the
+ * rest, rows [*m_main, m) over all columns and columns [*n_main, n) over rows
+ * [0, *m_main), each at most 16 wide. A C with at most 16 rows or columns may
+ * be computed by the thin kernel alone (*variant = -1, *m_main = *n_main = 0).
+ * Returns 0, or the 1-based position of the first invalid argument (bad
+ * transpose letter, m, n or k below 1, or a NULL output pointer). Pure host
+ * function: no HIP call.
+ */
+int mdg_dgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, int *variant,
+                   int64_t *m_main, int64_t *n_main);
 
 /* Number of kernel variants, and a static name for each (NULL if out of range). */
 int mdg_num_variants(void);

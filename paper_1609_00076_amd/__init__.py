@@ -10,7 +10,7 @@ from .binding import (MDG_ERR_DEVICE, MDG_ERR_HIP, MDG_ERR_SCRATCH, MDG_ERR_SIZE
                       MDG_SCHEDULE_LPT, MDG_SCHEDULE_NATURAL, MdgError, dgemm, gemm2d, gemm2d_args, load,
                       mdg_crt_bits, mdg_crt_max_moduli, mdg_crt_residues, mdg_dgemm, mdg_dgemm_crt,
                       mdg_dgemm_crt_workspace_size,
-                      mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_split, mdg_dgemm_split_noalloc,
+                      mdg_dgemm_ex, mdg_dgemm_grouped, mdg_dgemm_plan, mdg_dgemm_split, mdg_dgemm_split_noalloc,
                       mdg_dgemm_split_noalloc_max_bytes, mdg_dsyrk,
                       mdg_dsyrk_ex, mdg_dsyrk_select_variant, mdg_dtrmm, mdg_dtrsm,
                       mdg_dgemm_split_workspace_size, mdg_gemm_desc, mdg_grouped_plan,
@@ -23,7 +23,7 @@ __all__ = ["MDG_ERR_DEVICE", "MDG_ERR_HIP", "MDG_ERR_SCRATCH", "MDG_ERR_SIZE", "
            "MDG_SCHEDULE_LPT", "MDG_SCHEDULE_NATURAL", "MdgError", "dgemm", "gemm2d", "gemm2d_args", "load",
            "mdg_crt_bits", "mdg_crt_max_moduli", "mdg_crt_residues", "mdg_dgemm", "mdg_dgemm_crt",
            "mdg_dgemm_crt_workspace_size",
-           "mdg_dgemm_ex", "mdg_dgemm_grouped", "mdg_dgemm_split", "mdg_dgemm_split_noalloc",
+           "mdg_dgemm_ex", "mdg_dgemm_grouped", "mdg_dgemm_plan", "mdg_dgemm_split", "mdg_dgemm_split_noalloc",
            "mdg_dgemm_split_noalloc_max_bytes", "mdg_dgemm_split_workspace_size",
            "mdg_dsyrk", "mdg_dsyrk_ex", "mdg_dsyrk_select_variant", "mdg_dtrmm", "mdg_dtrsm",
            "mdg_gemm_desc", "mdg_grouped_plan", "mdg_grouped_plan_bytes",

@@ -79,6 +79,9 @@ def load():
     lib.mdg_dgemm_ex.restype = ci
     lib.mdg_select_variant.argtypes = [ch, ch, i64, i64, i64, dbl, dbl]
     lib.mdg_select_variant.restype = ci
+    lib.mdg_dgemm_plan.argtypes = [ch, ch, i64, i64, i64, ctypes.POINTER(ci),
+                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.mdg_dgemm_plan.restype = ci
     lib.mdg_num_variants.argtypes = []
     lib.mdg_num_variants.restype = ci
     lib.mdg_variant_name.argtypes = [ci]
@@ -265,6 +268,18 @@ def mdg_dtrsm(side, uplo, transa, diag, m, n, alpha, A, lda, B, ldb, stream=None
 def mdg_select_variant(transa, transb, m, n, k, alpha, beta) -> int:
     return load().mdg_select_variant(_ch(transa), _ch(transb), int(m), int(n), int(k),
                                      float(alpha), float(beta))
+
+
+def mdg_dgemm_plan(transa, transb, m, n, k):
+    """(variant, m_main, n_main) of the automatic dgemm: the tiled variant (or -1) covers rows
+    [0, m_main) and columns [0, n_main) of C, the thin kernel the rest. Raises MdgError on an
+    invalid argument."""
+    v, mm, nn = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+    st = load().mdg_dgemm_plan(_ch(transa), _ch(transb), int(m), int(n), int(k), ctypes.byref(v),
+                               ctypes.byref(mm), ctypes.byref(nn))
+    if st:
+        raise MdgError(st)
+    return v.value, mm.value, nn.value
 
 
 def mdg_num_variants() -> int:

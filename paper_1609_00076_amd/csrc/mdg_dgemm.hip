@@ -191,15 +191,14 @@ constexpr int tile_lds_doubles() {
   return 2 * C::KT * (LdsLayout<C, TA, TB>::A + LdsLayout<C, TA, TB>::B);
 }
 
-// Single GEMMs with a short k are bound by the old C streaming through HBM. For kPacedLo < k <=
-// kPacedHi their interior tiles write C paced when beta != 0, each store of a wave waiting for the
-// previous one to complete: the waves of a CU then leave the epilogue at staggered times, so that
-// some run their MFMA loop while others stream C. Measured on m = n = 8192, beta = 1: k = 64 runs
-// 5% faster (back to back) to 14% faster (within the full sweep), k = 128 and 256 the same; with
-// k <= 32 there is too little MFMA work to overlap and pacing costs 2-4%. The latency-bound tiles
-// of a grouped launch do not pace (pacing there measured 15% slower).
-constexpr int64_t kPacedLo = 32;
-constexpr int64_t kPacedHi = 256;
+// Single GEMMs with k <= kPacedK are bound by the old C streaming through HBM. Their interior
+// tiles write C paced when beta != 0: after every second store a wave waits until its stores have
+// completed. The waves of a CU then leave the epilogue at staggered times, so that some run their
+// MFMA loop while others stream C. Measured on m = n = 8192, beta = 1: k = 64 runs 6% faster back
+// to back and 15% faster within the full sweep, k = 16, 32, 128 and 256 the same to 1% faster
+// (waiting after every store instead cost 4% at k = 16). The latency-bound tiles of a grouped
+// launch do not pace (pacing there measured 15% slower).
+constexpr int64_t kPacedK = 256;
 
 // The whole computation of tile (tm, tn) of C by one workgroup; `smem` holds
 // tile_lds_doubles<C, TA, TB>() doubles. Shared by the single-GEMM kernels and the grouped one,
@@ -330,7 +329,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int tm, int tn, dou
 #pragma unroll
             for (int bi = 0; bi < C::BM; ++bi) {
               cbase[(16 * bj + 4 * r) * g.ldc + 16 * bi] = fma(beta, cb[bi][r], alpha * acc[bi][bj][r]);
-              __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this store has completed
+              if ((r * C::BM + bi) % 2 == 1) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
             }
         } else {
 #pragma unroll
@@ -378,7 +377,7 @@ dgemm_mfma_kernel(GemmArgs g, int tiles_m, int tiles_n) {
   __shared__ double smem[tile_lds_doubles<C, TA, TB>()];
   int tm, tn;
   if (!tile_coords(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
-  gemm_tile<C, TA, TB>(g, tm, tn, smem, g.k > kPacedLo && g.k <= kPacedHi);
+  gemm_tile<C, TA, TB>(g, tm, tn, smem, g.k <= kPacedK);
 }
 
 // C := beta*C over the logical m x n matrix (beta == 0 writes zeros without reading C). This is
@@ -391,6 +390,182 @@ __global__ void __launch_bounds__(256) scale_c_kernel(int64_t m, int64_t n, doub
     int64_t j = e / m, i = e - j * m;
     double* c = C + j * ldc + i;
     *c = (beta == 0.0) ? 0.0 : beta * *c;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Thin products: C blocks with at most kThinMax rows (or columns). Such a block needs the whole of
+// the other operand, read once from HBM, and a few multiply-adds per value read, so it is a
+// streaming kernel on the vector FMA units rather than MFMA tiles padded to 32 or more rows
+// (section 2.4's fringes taken out of the tiled product: see the plan in mdg_dgemm_ex). One form
+// covers both orientations:
+//   Out(i, l) := alpha * sum_q Y(i, q) X(q, l) + beta * Out(i, l),   i < s <= kThinMax, l < L,
+// with X (k x L) at X[q*x_q + l*x_l], Y (s x k) at Y[i*y_i + q*y_q] and Out at O[i*o_i + l*o_l].
+// A few rows of C: Y = those rows of op(A), X = op(B). A few columns: Y = op(B)^T restricted to
+// them, X = op(A)^T. Each workgroup owns kThinL consecutive l and the whole k range: chunks of
+// kThinKC k-values of X and Y are loaded with coalesced reads (along whichever of q or l has the
+// unit stride), staged in LDS, and each thread accumulates 4 l's by S rows over one k-residue
+// class mod 64; the 64 partial sums are then added in a fixed order (lanes, then waves), so the
+// result does not depend on timing.
+// ------------------------------------------------------------------------------------------------
+struct ThinArgs {
+  int64_t s, L, k;
+  const double* X;
+  int64_t x_q, x_l;
+  const double* Y;
+  int64_t y_i, y_q;
+  double* O;
+  int64_t o_i, o_l;
+  double alpha, beta;
+  int x_qfast, y_qfast;  // 1: the unit stride of X (of Y) runs along q; 0: along l (along i)
+};
+
+// Up to two thin blocks in one launch: workgroups [0, blocks0) take p[0], the rest p[1].
+struct ThinPair {
+  ThinArgs p[2];
+  int blocks0;
+};
+
+constexpr int kThinMax = 16;          // largest thin side
+constexpr int kThinL = 16;            // outputs along l per workgroup
+constexpr int kThinKC = 256;          // k-values per staged chunk
+constexpr int kThinXS = kThinL + 2;   // LDS row stride of the X chunk (rows stay 16-byte aligned)
+constexpr int kThinYS = kThinKC + 2;  // LDS row stride of the Y chunk
+// Largest leading dimension the thin kernel's 32-bit element offsets within a chunk allow.
+constexpr int64_t kThinMaxLd = (int64_t)INT32_MAX / (kThinKC + kThinMax);
+
+// The body for one layout of X (XQ: unit stride along q) and of Y (YQ: unit stride along q).
+// Addresses are formed from a per-chunk base (uniform) plus a 32-bit element offset: the host
+// only takes this path when (kThinKC-1)*|q stride| + (kThinL-1 or S-1)*|other stride| < 2^31.
+// Two chunks are in flight: while one is multiplied out of LDS the next two are loading.
+template <int S, bool XQ, bool YQ>
+__device__ __forceinline__ void thin_body(const ThinArgs& a, int64_t l0, double* xs, double* ys) {
+  const int t = threadIdx.x;
+  // Element r of this thread's share of a chunk: X (16 per thread) and Y (S per thread). With
+  // the unit stride along q a wave reads 64 consecutive q of one l (of one i); otherwise 4 rows
+  // of 16 consecutive l (S consecutive i per q).
+  const int xq0 = XQ ? t : (t >> 4), xl0 = XQ ? 0 : (t & 15);  // q = xq0 + xqs*r, l = xl0 + xls*r
+  constexpr int xqs = XQ ? 0 : 16, xls = XQ ? 1 : 0;
+  const int yi0 = YQ ? 0 : (t % S), yq0 = YQ ? t : t / S;
+  constexpr int yis = YQ ? 1 : 0, yqs = YQ ? 0 : kThinKC / S;
+  const int l_last = (int)min<int64_t>(a.L - 1 - l0, kThinL - 1);  // last valid l of this block
+  const int i_last = (int)(a.s - 1);
+  const int xq = (int)a.x_q, xl = (int)a.x_l, yi = (int)a.y_i, yq = (int)a.y_q;
+
+  auto load_chunk = [&](int64_t q0, double (&xr)[16], double (&yr)[S]) {
+    const int q_last = (int)min<int64_t>(a.k - 1 - q0, kThinKC - 1);
+    const double* xb = a.X + q0 * a.x_q + l0 * a.x_l;
+    const double* yb = a.Y + q0 * a.y_q;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int q = min(xq0 + xqs * r, q_last), l = min(xl0 + xls * r, l_last);
+      xr[r] = xb[q * xq + l * xl];
+    }
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const int i = min(yi0 + yis * r, i_last), q = min(yq0 + yqs * r, q_last);
+      yr[r] = yb[i * yi + q * yq];
+    }
+  };
+  // Values outside the operands (q >= k, l >= L, i >= s) go to LDS as zeros.
+  auto store_chunk = [&](int64_t q0, const double (&xr)[16], const double (&yr)[S]) {
+    const int64_t q_end = a.k - q0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int q = xq0 + xqs * r, l = xl0 + xls * r;
+      xs[q * kThinXS + l] = (q < q_end && l <= l_last) ? xr[r] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const int i = yi0 + yis * r, q = yq0 + yqs * r;
+      ys[i * kThinYS + q] = (q < q_end && i <= i_last) ? yr[r] : 0.0;
+    }
+  };
+
+  const int lq = t & 3, g = t >> 2;  // l = 4*lq .. 4*lq+3, k-residue g mod 64
+  double acc[S][4];
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[i][u] = 0.0;
+  auto multiply = [&]() {
+#pragma unroll
+    for (int j = 0; j < kThinKC / 64; ++j) {
+      const int q = g + 64 * j;
+      const double2 x01 = *reinterpret_cast<const double2*>(&xs[q * kThinXS + 4 * lq]);
+      const double2 x23 = *reinterpret_cast<const double2*>(&xs[q * kThinXS + 4 * lq + 2]);
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        const double y = ys[i * kThinYS + q];
+        acc[i][0] = fma(y, x01.x, acc[i][0]);
+        acc[i][1] = fma(y, x01.y, acc[i][1]);
+        acc[i][2] = fma(y, x23.x, acc[i][2]);
+        acc[i][3] = fma(y, x23.y, acc[i][3]);
+      }
+    }
+  };
+
+  const int64_t chunks = (a.k + kThinKC - 1) / kThinKC;
+  double xa[16], ya[S], xb[16], yb[S];
+  load_chunk(0, xa, ya);
+  if (chunks > 1) load_chunk(kThinKC, xb, yb);
+  for (int64_t c = 0; c < chunks; c += 2) {
+    if (c > 0) __syncthreads();  // the previous chunk has been read
+    store_chunk(c * kThinKC, xa, ya);
+    __syncthreads();
+    if (c + 2 < chunks) load_chunk((c + 2) * kThinKC, xa, ya);
+    multiply();
+    if (c + 1 >= chunks) break;
+    __syncthreads();
+    store_chunk((c + 1) * kThinKC, xb, yb);
+    __syncthreads();
+    if (c + 3 < chunks) load_chunk((c + 3) * kThinKC, xb, yb);
+    multiply();
+  }
+
+  // The 16 residue classes of a wave (lane bits 2..5), then the 4 waves in order.
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int off = 4; off < 64; off <<= 1) acc[i][u] += __shfl_xor(acc[i][u], off);
+  __syncthreads();  // xs is reused for the per-wave sums
+  double* red = xs;  // [wave][i][l]
+  const int wave = t >> 6;
+  if ((t & 63) < 4) {
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) red[(wave * S + i) * kThinL + 4 * lq + u] = acc[i][u];
+  }
+  __syncthreads();
+  if (t < S * kThinL) {
+    const int i = t / kThinL, l = t % kThinL;
+    if (i <= i_last && l <= l_last) {
+      const double sum = ((red[i * kThinL + l] + red[(S + i) * kThinL + l]) +
+                          red[(2 * S + i) * kThinL + l]) + red[(3 * S + i) * kThinL + l];
+      double* o = a.O + i * a.o_i + (l0 + l) * a.o_l;
+      const double v = a.alpha * sum;
+      *o = (a.beta != 0.0) ? fma(a.beta, *o, v) : v;
+    }
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) thin_kernel(ThinPair tp) {
+  static_assert(S == 4 || S == 8 || S == 16, "thin side bucket");
+  __shared__ __align__(16) double xs[kThinKC * kThinXS];
+  __shared__ double ys[S * kThinYS];
+  const bool second = (int)blockIdx.x >= tp.blocks0;
+  const ThinArgs& a = second ? tp.p[1] : tp.p[0];
+  const int64_t l0 = (int64_t)(second ? (int)blockIdx.x - tp.blocks0 : (int)blockIdx.x) * kThinL;
+  if (a.x_qfast) {
+    if (a.y_qfast) thin_body<S, true, true>(a, l0, xs, ys);
+    else           thin_body<S, true, false>(a, l0, xs, ys);
+  } else {
+    if (a.y_qfast) thin_body<S, false, true>(a, l0, xs, ys);
+    else           thin_body<S, false, false>(a, l0, xs, ys);
   }
 }
 
@@ -1398,35 +1573,105 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr double kTileOverheadK = 128.0;
 constexpr int64_t kShortK = 256;
 
-int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
+// The model's estimate for one variant (in multiply-adds per CU at the variant's efficiency), or
+// a negative value when the variant has no efficiency for this regime.
+double tile_cost(const Variant& var, bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
+  const bool short_k = k <= kShortK;
+  const int eff = short_k ? var.short_k_permil : var.eff_permil[ta][tb];
+  if (eff <= 0) return -1.0;
+  const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
+  const int64_t per_cu = ceil_div(tiles, kCUs);
+  const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
+  const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
+  const double overhead = short_k ? 0.0 : kTileOverheadK / resident;
+  return (double)per_cu * var.mt * var.nt * ((double)k + overhead) / (eff * 1e-3 * occupancy);
+}
+
+// The one-group variant of least estimate, and that estimate.
+int pick_one_group(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double* cost) {
   int best = 0;
   double best_cost = 0.0;
-  const bool short_k = k <= kShortK;
   for (int v = 0; v < kNumVariants; ++v) {
-    const Variant& var = kVariants[v];
-    const int eff = short_k ? var.short_k_permil : var.eff_permil[ta][tb];
-    if (eff <= 0) continue;
-    const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
-    const int64_t per_cu = ceil_div(tiles, kCUs);
-    const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
-    const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
-    const double overhead = short_k ? 0.0 : kTileOverheadK / resident;
-    const double cost = (double)per_cu * var.mt * var.nt * ((double)k + overhead) /
-                        (eff * 1e-3 * occupancy);
-    if (best_cost == 0.0 || cost < best_cost) {
+    const double c = tile_cost(kVariants[v], ta, tb, m, n, k);
+    if (c < 0.0) continue;
+    if (best_cost == 0.0 || c < best_cost) {
       best = v;
-      best_cost = cost;
+      best_cost = c;
     }
   }
-  // A grid of at most one workgroup per CU leaves each SIMD one wave of a one-group tile; the
-  // k-split configuration of the same tile runs two per SIMD there (measured at 1024^3: 8% faster;
-  // with two or more tiles per CU the one-group form is as fast or faster).
-  const Variant& b = kVariants[best];
-  if (!short_k && b.ks == 1 &&
-      ceil_div(m, b.mt) * ceil_div(n, b.nt) <= kCUs) {
-    for (int v = 0; v < kNumVariants; ++v)
-      if (kVariants[v].ks == 2 && kVariants[v].mt == b.mt && kVariants[v].nt == b.nt) return v;
+  *cost = best_cost;
+  return best;
+}
+
+// A grid of at most one workgroup per CU leaves each SIMD one wave of a one-group tile; the
+// k-split configuration of the same tile runs two per SIMD there (measured at 1024^3: 8% faster;
+// with two or more tiles per CU the one-group form is as fast or faster).
+int with_k_split(int v, int64_t m, int64_t n, int64_t k) {
+  const Variant& b = kVariants[v];
+  if (k > kShortK && b.ks == 1 && ceil_div(m, b.mt) * ceil_div(n, b.nt) <= kCUs) {
+    for (int w = 0; w < kNumVariants; ++w)
+      if (kVariants[w].ks == 2 && kVariants[w].mt == b.mt && kVariants[w].nt == b.nt) return w;
   }
+  return v;
+}
+
+int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
+  double cost;
+  return with_k_split(pick_one_group(ta, tb, m, n, k, &cost), m, n, k);
+}
+
+// Plan of an automatic dgemm: the variant `vid` computes the block of rows [0, m0) and columns
+// [0, n0) of C (vid = -1: no tiled block); the thin kernel computes rows [m0, m) over all
+// columns and columns [n0, n) over rows [0, m0). Each thin side is at most kThinMax wide.
+struct DgemmPlan {
+  int vid;
+  int64_t m0, n0;
+};
+
+// Estimates of the thin kernel in the model's units: its HBM bytes (the long operand once, C read
+// and written) at kThinBytesPerSec plus one launch, converted at the CUs' multiply-add rate.
+constexpr double kThinBytesPerSec = 4.0e12;
+constexpr double kLaunchSec = 5e-6;
+constexpr double kCuMacPerSec = 64.0 * 2.4e9;  // FP64 multiply-adds per second of one CU
+// A fringe is split off only when the estimate drops by this factor (the model is coarse).
+constexpr double kSplitGain = 0.95;
+
+double thin_bytes(int64_t L, int64_t s, int64_t k) { return 8.0 * ((double)k * L + 2.0 * s * L); }
+
+double thin_cost(double bytes) { return (bytes / kThinBytesPerSec + kLaunchSec) * kCuMacPerSec; }
+
+DgemmPlan plan_dgemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
+  double best_cost;
+  DgemmPlan best{pick_one_group(ta, tb, m, n, k, &best_cost), m, n};
+  if (m <= kThinMax || n <= kThinMax) {
+    const bool rows = m <= n;  // the thinner side
+    const double c = thin_cost(rows ? thin_bytes(n, m, k) : thin_bytes(m, n, k));
+    if (c < best_cost) {
+      best = rows ? DgemmPlan{-1, 0, n} : DgemmPlan{-1, m, 0};
+      best_cost = c;
+    }
+  }
+  // Big tiles over the largest block they divide, when what is left over is thin.
+  DgemmPlan split{-1, m, n};
+  double split_cost = 0.0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    const Variant& var = kVariants[v];
+    if (var.ks != 1) continue;
+    const int64_t rm = m % var.mt, rn = n % var.nt;
+    const int64_t m0 = (rm != 0 && rm <= kThinMax && m > var.mt) ? m - rm : m;
+    const int64_t n0 = (rn != 0 && rn <= kThinMax && n > var.nt) ? n - rn : n;
+    if (m0 == m && n0 == n) continue;
+    const double c0 = tile_cost(var, ta, tb, m0, n0, k);
+    if (c0 < 0.0) continue;
+    const double c = c0 + thin_cost((m0 < m ? thin_bytes(n, m - m0, k) : 0.0) +
+                                    (n0 < n ? thin_bytes(m0, n - n0, k) : 0.0));
+    if (split_cost == 0.0 || c < split_cost) {
+      split = DgemmPlan{v, m0, n0};
+      split_cost = c;
+    }
+  }
+  if (split.vid >= 0 && split_cost < best_cost * kSplitGain) best = split;
+  if (best.vid >= 0) best.vid = with_k_split(best.vid, best.m0, best.n0, k);
   return best;
 }
 
@@ -1588,7 +1833,24 @@ int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k
   if (!(is_notrans(transa) || is_trans(transa)) || !(is_notrans(transb) || is_trans(transb)))
     return -1;
   if (m <= 0 || n <= 0 || k <= 0 || alpha == 0.0) return -1;
-  return pick_variant(is_trans(transa), is_trans(transb), m, n, k);
+  return plan_dgemm(is_trans(transa), is_trans(transb), m, n, k).vid;
+}
+
+int mdg_dgemm_plan(char transa, char transb, int64_t m, int64_t n, int64_t k, int* variant,
+                   int64_t* m_main, int64_t* n_main) {
+  if (!(is_notrans(transa) || is_trans(transa))) return 1;
+  if (!(is_notrans(transb) || is_trans(transb))) return 2;
+  if (m <= 0) return 3;
+  if (n <= 0) return 4;
+  if (k <= 0) return 5;
+  if (!variant) return 6;
+  if (!m_main) return 7;
+  if (!n_main) return 8;
+  const DgemmPlan pl = plan_dgemm(is_trans(transa), is_trans(transb), m, n, k);
+  *variant = pl.vid;
+  *m_main = pl.vid >= 0 ? pl.m0 : 0;
+  *n_main = pl.vid >= 0 ? pl.n0 : 0;
+  return MDG_SUCCESS;
 }
 
 }  // extern "C"
@@ -1596,12 +1858,13 @@ int mdg_select_variant(char transa, char transb, int64_t m, int64_t n, int64_t k
 namespace mdg_impl {
 
 // Every check mdg_dgemm_ex makes before its first HIP call. Returns the status it would return
-// there (nonzero), or 0 with *vid the variant to launch (-1: the alpha == 0 / k == 0 scaling,
-// -2: nothing to enqueue).
+// there (nonzero), or 0 with *plan what to launch: plan->vid = -2 nothing; when alpha == 0 or
+// k == 0 (and beta != 1) the scaling of C; otherwise the plan (an explicit variant covers all
+// of C).
 int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
                   double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
-                  double beta, const double* C, int64_t ldc, int* vid) {
-  *vid = -2;
+                  double beta, const double* C, int64_t ldc, DgemmPlan* plan) {
+  *plan = DgemmPlan{-2, m, n};
   const int info = check_args(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   if (info) return info;
   if (variant != MDG_VARIANT_AUTO && (variant < 0 || variant >= kNumVariants))
@@ -1610,18 +1873,23 @@ int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, i
   const bool no_product = (alpha == 0.0 || k == 0);
   if (no_product && beta == 1.0) return MDG_SUCCESS;
   if (no_product) {
-    *vid = -1;
+    *plan = DgemmPlan{-1, m, n};
     return MDG_SUCCESS;
   }
-  const int v_id = (variant == MDG_VARIANT_AUTO)
-                       ? pick_variant(is_trans(transa), is_trans(transb), m, n, k)
-                       : variant;
-  const Variant& v = kVariants[v_id];
-  if (ceil_div(m, v.mt) * ceil_div(n, v.nt) > (int64_t)INT32_MAX / 1024)
-    return MDG_ERR_SIZE;  // beyond one launch's grid
-  if (!panel_offsets_fit(is_trans(transa), is_trans(transb), v.mt, v.nt, v.kt, m, n, k, lda, ldb))
-    return MDG_ERR_SIZE;
-  *vid = v_id;
+  const bool ta = is_trans(transa), tb = is_trans(transb);
+  DgemmPlan pl =
+      (variant == MDG_VARIANT_AUTO) ? plan_dgemm(ta, tb, m, n, k) : DgemmPlan{variant, m, n};
+  if ((pl.m0 < m || pl.n0 < n) && std::max(lda, ldb) > kThinMaxLd)
+    pl = DgemmPlan{pick_variant(ta, tb, m, n, k), m, n};  // offsets beyond the thin kernel's
+  if (pl.vid >= 0) {
+    const Variant& v = kVariants[pl.vid];
+    if (ceil_div(pl.m0, v.mt) * ceil_div(pl.n0, v.nt) > (int64_t)INT32_MAX / 1024)
+      return MDG_ERR_SIZE;  // beyond one launch's grid
+    if (!panel_offsets_fit(ta, tb, v.mt, v.nt, v.kt, pl.m0, pl.n0, k, lda, ldb))
+      return MDG_ERR_SIZE;
+  }
+  if (ceil_div(m, kThinL) + ceil_div(n, kThinL) > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;
+  *plan = pl;
   return MDG_SUCCESS;
 }
 
@@ -1630,9 +1898,9 @@ int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, i
 int mdg_dgemm_precheck(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,
                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                        const double* C, int64_t ldc) {
-  int vid;
+  DgemmPlan plan;
   return dgemm_prepare(MDG_VARIANT_AUTO, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
-                       ldc, &vid);
+                       ldc, &plan);
 }
 
 int mdg_device_check(void) { return device_check(); }
@@ -1642,33 +1910,71 @@ extern "C" {
 int mdg_dgemm_ex(int variant, char transa, char transb, int64_t m, int64_t n, int64_t k,
                  double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                  double beta, double* C, int64_t ldc, void* stream) {
-  int vid;
+  DgemmPlan plan;
   const int st = dgemm_prepare(variant, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
-                               ldc, &vid);
-  if (st || vid == -2) return st;
-  const bool no_product = vid == -1;
+                               ldc, &plan);
+  if (st || plan.vid == -2) return st;
   const int dc = device_check();
   if (dc) return dc;
   hipStream_t s = static_cast<hipStream_t>(stream);
 
-  if (no_product) {
+  if (alpha == 0.0 || k == 0) {
     const int64_t total = m * n;
     const int64_t blocks = ceil_div(total, 256) < 65536 ? ceil_div(total, 256) : 65536;
     return launch(reinterpret_cast<const void*>(&scale_c_kernel), dim3((unsigned)blocks), dim3(256),
                   s, m, n, beta, C, ldc);
   }
 
-  const Variant& v = kVariants[vid];
-  const int64_t tiles_m = ceil_div(m, v.mt), tiles_n = ceil_div(n, v.nt);
-  const int64_t tiles = tiles_m * tiles_n;
-  const int64_t rows_a = is_trans(transa) ? k : m, cols_a = is_trans(transa) ? m : k;
-  const int64_t rows_b = is_trans(transb) ? n : k, cols_b = is_trans(transb) ? k : n;
-  GemmArgs g{m, n, k, lda, ldb, ldc, alpha, beta, A, B, C,
-             (cols_a - 1) * lda + rows_a, (cols_b - 1) * ldb + rows_b};
-  KernelFn fn = v.fn[is_trans(transa) ? 1 : 0][is_trans(transb) ? 1 : 0];
-  const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;  // see tile_coords
-  return launch(reinterpret_cast<const void*>(fn), dim3((unsigned)grid), dim3(v.threads), s, g,
-                (int)tiles_m, (int)tiles_n);
+  const bool ta = is_trans(transa), tb = is_trans(transb);
+  if (plan.vid >= 0) {
+    const int64_t mm = plan.m0, nn = plan.n0;
+    const Variant& v = kVariants[plan.vid];
+    const int64_t tiles_m = ceil_div(mm, v.mt), tiles_n = ceil_div(nn, v.nt);
+    const int64_t tiles = tiles_m * tiles_n;
+    const int64_t rows_a = ta ? k : mm, cols_a = ta ? mm : k;
+    const int64_t rows_b = tb ? nn : k, cols_b = tb ? k : nn;
+    GemmArgs g{mm, nn, k, lda, ldb, ldc, alpha, beta, A, B, C,
+               (cols_a - 1) * lda + rows_a, (cols_b - 1) * ldb + rows_b};
+    KernelFn fn = v.fn[ta ? 1 : 0][tb ? 1 : 0];
+    const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;  // see tile_coords
+    const int r = launch(reinterpret_cast<const void*>(fn), dim3((unsigned)grid), dim3(v.threads),
+                         s, g, (int)tiles_m, (int)tiles_n);
+    if (r) return r;
+  }
+
+  // The thin fringes: rows [m0, m) over all columns, columns [n0, n) over rows [0, m0).
+  ThinPair tp{};
+  int parts = 0, side = 0;
+  int64_t blocks = 0;
+  if (plan.m0 < m) {  // op(A) rows m0.. times op(B)
+    const int64_t r0 = plan.m0;
+    tp.p[parts] = ThinArgs{m - r0, n, k,
+                           B, tb ? ldb : 1, tb ? 1 : ldb,
+                           ta ? A + r0 * lda : A + r0, ta ? lda : 1, ta ? 1 : lda,
+                           C + r0, 1, ldc,
+                           alpha, beta, tb ? 0 : 1, ta ? 1 : 0};
+    side = std::max<int>(side, (int)(m - r0));
+    blocks += ceil_div(n, kThinL);
+    if (parts == 0) tp.blocks0 = (int)blocks;
+    ++parts;
+  }
+  if (plan.n0 < n && plan.m0 > 0) {  // op(A) rows 0..m0 times op(B) columns n0..
+    const int64_t c0 = plan.n0;
+    tp.p[parts] = ThinArgs{n - c0, plan.m0, k,
+                           A, ta ? 1 : lda, ta ? lda : 1,
+                           tb ? B + c0 : B + c0 * ldb, tb ? 1 : ldb, tb ? ldb : 1,
+                           C + c0 * ldc, ldc, 1,
+                           alpha, beta, ta ? 1 : 0, tb ? 0 : 1};
+    side = std::max<int>(side, (int)(n - c0));
+    blocks += ceil_div(plan.m0, kThinL);
+    if (parts == 0) tp.blocks0 = (int)blocks;
+    ++parts;
+  }
+  if (parts == 0) return MDG_SUCCESS;
+  const void* fn = side <= 4   ? reinterpret_cast<const void*>(&thin_kernel<4>)
+                   : side <= 8 ? reinterpret_cast<const void*>(&thin_kernel<8>)
+                               : reinterpret_cast<const void*>(&thin_kernel<16>);
+  return launch(fn, dim3((unsigned)blocks), dim3(256), s, tp);
 }
 
 int mdg_dgemm(char transa, char transb, int64_t m, int64_t n, int64_t k, double alpha,

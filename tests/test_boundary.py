@@ -150,6 +150,30 @@ def test_sweep_variant_choice():
             assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"
 
 
+def test_dgemm_plan_splits_off_thin_fringes():
+    """A fringe of at most 16 rows or columns left by the big tiles goes to the thin kernel; the
+    tiled block takes the variant of the divisible size. Thin products go to the thin kernel
+    alone; sizes the big tiles divide are not split."""
+    plan = mdg.mdg_dgemm_plan
+    for ta in "NT":
+        for tb in "NT":
+            whole = mdg.mdg_select_variant(ta, tb, 4096, 4096, 4096, 1.0, 1.0)
+            assert plan(ta, tb, 4096, 4096, 4096) == (whole, 4096, 4096)
+            for size in (4097, 4099, 4112):
+                v, m0, n0 = plan(ta, tb, size, size, size)
+                assert (v, m0, n0) == (whole, 4096, 4096), (ta, tb, size)
+                assert mdg.mdg_select_variant(ta, tb, size, size, size, 1.0, 1.0) == v
+            assert plan(ta, tb, 4113, 4113, 4113)[1:] == (4113, 4113)  # fringe of 17: no split
+            for m, n, k in ((3, 4099, 4099), (4099, 3, 4099), (16, 5000, 300), (1, 1, 4000)):
+                assert plan(ta, tb, m, n, k) == (-1, 0, 0)
+                assert mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0) == -1
+    for args, pos in ((("X", "N", 4, 4, 4), 1), (("N", "Y", 4, 4, 4), 2), (("N", "N", 0, 4, 4), 3),
+                      (("N", "N", 4, -1, 4), 4), (("N", "N", 4, 4, 0), 5)):
+        with pytest.raises(mdg.MdgError) as e:
+            plan(*args)
+        assert e.value.status == pos
+
+
 def test_every_variant_is_reachable():
     """No dead entries in the kernel table: each variant is the automatic choice for some shape and
     transpose case, a grouped tile class, or a dsyrk configuration."""
@@ -182,7 +206,7 @@ def test_single_round_grids_take_the_k_split_tile():
         for tb in "NT":
             for m, n, k in ((1024, 1024, 1024), (1000, 1000, 300), (512, 2048, 4096)):
                 assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
-            for m, n, k in ((1024, 1024, 256), (1025, 1024, 1024), (2048, 2048, 2048),
+            for m, n, k in ((1024, 1024, 256), (1089, 1024, 1024), (2048, 2048, 2048),
                             (8192, 8192, 8192)):
                 assert not name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
 

@@ -107,8 +107,10 @@ def traffic_from(dirs, copy_bytes, mdg):
     """Write TRAFFIC_FILE from four rocprofv3 --pmc runs: FETCH_SIZE and WRITE_SIZE of one sweep
     step (bench.py --steps 1 --warmup 0 --cpu-budget 0), then of the copy calibration
     (bench.py --copy-calibration copy_bytes). The sweep's GEMM dispatches are matched to its
-    problems in launch order; each counter (KiB per dispatch) is scaled by the factor that maps its
-    reading for one copy of copy_bytes to the bytes the copy reads (FETCH) or writes (WRITE)."""
+    problems in launch order (thin-kernel launches are not GEMM dispatches here: a split
+    problem's figures are its tiled block's); each counter (KiB per dispatch) is scaled by the
+    factor that maps its reading for one copy of copy_bytes to the bytes the copy reads (FETCH)
+    or writes (WRITE)."""
     f_dir, w_dir, cf_dir, cw_dir = dirs
     def scale(run_dir, counter):
         vals = [v for _, (name, v) in sorted(read_counter(run_dir, counter).items())]
@@ -128,7 +130,9 @@ def traffic_from(dirs, copy_bytes, mdg):
             d = per.setdefault(kernel_key(mdg, p), dict(meas=0.0, alg=0.0, n=0, shapes=set()))
             d["meas"] += v * 1024.0 * sc
             if counter == "FETCH_SIZE":
-                d["alg"] += hbm_bytes(p)
+                # the tiled block only, where a thin launch takes the fringe rows and columns
+                _, m0, n0 = mdg.mdg_dgemm_plan(p["transa"], p["transb"], p["m"], p["n"], p["k"])
+                d["alg"] += hbm_bytes(dict(p, m=m0 or p["m"], n=n0 or p["n"]))
                 d["n"] += 1
                 d["shapes"].add(f"{p['m']}x{p['n']}x{p['k']}")
     out = {"source_sha": source_hash(), "workload": out_workload(probs), "fetch_scale": fs,
@@ -192,9 +196,14 @@ def hbm_bytes(p, beta=1.0):
 
 
 def kernel_key(mdg, p, variant=-1):
-    v = variant if variant >= 0 else \
-        mdg.mdg_select_variant(p["transa"], p["transb"], p["m"], p["n"], p["k"], 1.0, 1.0)
-    return f"{mdg.mdg_variant_name(v)}[{p['transa']}{p['transb']}]"
+    """The variant a problem launches; an automatic call whose plan splits thin fringe rows or
+    columns off the tiled block (a second, thin-kernel launch) gets its own key."""
+    if variant >= 0:
+        return f"{mdg.mdg_variant_name(variant)}[{p['transa']}{p['transb']}]"
+    v, m0, n0 = mdg.mdg_dgemm_plan(p["transa"], p["transb"], p["m"], p["n"], p["k"])
+    name = mdg.mdg_variant_name(v) if v >= 0 else "thin"
+    split = "+thin" if 0 <= v and (m0 < p["m"] or n0 < p["n"]) else ""
+    return f"{name}{split}[{p['transa']}{p['transb']}]"
 
 
 def run_step(mdg, probs, events=None, variant=-1):

@@ -1275,6 +1275,8 @@ using Ring128x256t = RingCfg<128, 256, 128, 32, 3, 2, 1>;  // 8 waves of 128x32 
 // Two k-groups of 4 waves of 32x32 on a 64x64 tile, 4 stages: two waves per SIMD with one
 // workgroup per CU.
 using Ring64k2 = RingCfg<64, 64, 32, 32, 4, 2, 1, 2>;
+// Two k-groups of 4 waves of 64x64 on a 128x128 tile, 2 stages (139 KB of LDS).
+using Ring128k2 = RingCfg<128, 128, 64, 64, 2, 2, 1, 2>;
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -1286,7 +1288,8 @@ struct Variant {
   int wgs_per_cu;   // workgroups resident per CU (LDS- and register-limited)
   int eff_permil[2][2];  // [transa][transb]: measured share of the FP64 MFMA peak on large
                          // square shapes, per mille; 0 keeps the variant out of the automatic
-                         // choice
+                         // choice. For a two-group variant: the share measured on grids of at
+                         // most one tile per CU, the only grids it is priced on
   int short_k_permil;    // the same share measured on m = n = 8192, k = 64 (HBM-bound: the old
                          // C streams in and out); 0 keeps the variant out of the choice for
                          // k <= kShortK
@@ -1361,6 +1364,8 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
     make_wave_variant("wave_f64_64x64x8_w32x32", 0),
     make_ring_variant<Ring64k2>("ringk2_f64_64x64x16_w32x32_s4", 0),
+    // one round of 128x128 tiles: 2048^3 and 2048^2 x 8192 at 69.6-73.7 TFLOP/s
+    make_ring_variant<Ring128k2>("ringk2_f64_128x128x16_w64x64_s2", Eff(946, 946, 946, 946)),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1568,8 +1573,9 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // the earlier entry.
 // For k <= kShortK the GEMM is bound by the old C streaming through HBM rather than by the
 // MFMAs, and the variants are ranked by their efficiency measured on such a shape (which already
-// includes the epilogue). Variants with two k-groups have no efficiency of their own: one replaces
-// the chosen one-group variant of the same tile when the grid is a single round (below).
+// includes the epilogue). Variants with two k-groups are priced only on grids of at most one tile
+// per CU, with an efficiency measured there (or none: then one replaces the chosen one-group
+// variant of the same tile when the grid is a single round, below).
 constexpr double kTileOverheadK = 128.0;
 constexpr int64_t kShortK = 256;
 
@@ -1580,6 +1586,7 @@ double tile_cost(const Variant& var, bool ta, bool tb, int64_t m, int64_t n, int
   const int eff = short_k ? var.short_k_permil : var.eff_permil[ta][tb];
   if (eff <= 0) return -1.0;
   const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
+  if (var.ks != 1 && tiles > kCUs) return -1.0;  // two k-groups pay off on one round only
   const int64_t per_cu = ceil_div(tiles, kCUs);
   const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
   const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);
@@ -1587,8 +1594,8 @@ double tile_cost(const Variant& var, bool ta, bool tb, int64_t m, int64_t n, int
   return (double)per_cu * var.mt * var.nt * ((double)k + overhead) / (eff * 1e-3 * occupancy);
 }
 
-// The one-group variant of least estimate, and that estimate.
-int pick_one_group(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double* cost) {
+// The variant of least estimate, and that estimate.
+int pick_by_cost(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double* cost) {
   int best = 0;
   double best_cost = 0.0;
   for (int v = 0; v < kNumVariants; ++v) {
@@ -1617,7 +1624,7 @@ int with_k_split(int v, int64_t m, int64_t n, int64_t k) {
 
 int pick_variant(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
   double cost;
-  return with_k_split(pick_one_group(ta, tb, m, n, k, &cost), m, n, k);
+  return with_k_split(pick_by_cost(ta, tb, m, n, k, &cost), m, n, k);
 }
 
 // Plan of an automatic dgemm: the variant `vid` computes the block of rows [0, m0) and columns
@@ -1642,7 +1649,7 @@ double thin_cost(double bytes) { return (bytes / kThinBytesPerSec + kLaunchSec) 
 
 DgemmPlan plan_dgemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
   double best_cost;
-  DgemmPlan best{pick_one_group(ta, tb, m, n, k, &best_cost), m, n};
+  DgemmPlan best{pick_by_cost(ta, tb, m, n, k, &best_cost), m, n};
   if (m <= kThinMax || n <= kThinMax) {
     const bool rows = m <= n;  // the thinner side
     const double c = thin_cost(rows ? thin_bytes(n, m, k) : thin_bytes(m, n, k));
@@ -1656,7 +1663,6 @@ DgemmPlan plan_dgemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k) {
   double split_cost = 0.0;
   for (int v = 0; v < kNumVariants; ++v) {
     const Variant& var = kVariants[v];
-    if (var.ks != 1) continue;
     const int64_t rm = m % var.mt, rn = n % var.nt;
     const int64_t m0 = (rm != 0 && rm <= kThinMax && m > var.mt) ? m - rm : m;
     const int64_t n0 = (rn != 0 && rn <= kThinMax && n > var.nt) ? n - rn : n;

@@ -132,9 +132,9 @@ def test_leading_dimension_offset_guard_is_host_side_and_exact():
 
 def test_sweep_variant_choice():
     """The measured choice for the sweep shapes (each a variant whose efficiency was measured on the
-    GPU for that transpose case): 256x128 or 128x256 ring tiles from 4096 up, smaller ring tiles for
-    2048 to 4099, the k-split 64x64 ring tile for 1024 (one tile per CU), the register-staged
-    128x64 tile for the HBM-bound k = 64 case."""
+    GPU for that transpose case): 256x128 or 128x256 ring tiles from 4096 up (4099 on its 4096
+    block), the k-split 128x128 ring tile for 2048 and the k-split 64x64 one for 1024 (one tile per
+    CU), the register-staged 128x64 tile for the HBM-bound k = 64 case."""
     def name(ta, tb, m, n, k):
         return mdg.mdg_variant_name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0))
     want = {"NN": "ring_f64_128x256x16_w128x32_s3_il", "NT": "ring_f64_128x256x16_w64x64_s3_il",
@@ -146,7 +146,7 @@ def test_sweep_variant_choice():
     for ta in "NT":
         for tb in "NT":
             assert name(ta, tb, 1024, 1024, 1024) == "ringk2_f64_64x64x16_w32x32_s4"
-            assert name(ta, tb, 2048, 2048, 2048).startswith("ring_f64_128x")
+            assert name(ta, tb, 2048, 2048, 2048) == "ringk2_f64_128x128x16_w64x64_s2"
             assert name(ta, tb, 8192, 8192, 64) == "mfma_f64_128x64x16_w32x32"
 
 
@@ -199,16 +199,19 @@ def test_every_variant_is_reachable():
 
 def test_single_round_grids_take_the_k_split_tile():
     """A grid of at most one 64x64 tile per CU (256 CUs) with k above the short-k bound runs the
-    k-split configuration of that tile; more tiles, short k or other tiles keep the one-group
-    choice."""
+    k-split configuration of that tile; more tiles or short k keep the one-group choice. One round
+    of 128x128 tiles that fills most of the GPU runs the k-split 128x128 tile."""
     name = mdg.mdg_variant_name
     for ta in "NT":
         for tb in "NT":
             for m, n, k in ((1024, 1024, 1024), (1000, 1000, 300), (512, 2048, 4096)):
                 assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
-            for m, n, k in ((1024, 1024, 256), (1089, 1024, 1024), (2048, 2048, 2048),
+            for m, n, k in ((1024, 1024, 256), (1089, 1024, 1024), (1536, 1536, 2048),
                             (8192, 8192, 8192)):
                 assert not name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
+            for m, n, k in ((2048, 2048, 2048), (2048, 2048, 8192), (642, 4924, 4096)):
+                assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)) == \
+                    "ringk2_f64_128x128x16_w64x64_s2"
 
 
 # ---- level-3 entry points: checks and refusals that return before any HIP call ----------------

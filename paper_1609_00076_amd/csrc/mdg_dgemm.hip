@@ -777,8 +777,9 @@ struct RingCfg {
   static_assert(MT % WM == 0 && NT % WN == 0 && WM % 16 == 0 && WN % 16 == 0, "wave grid");
   static_assert(STAGES >= 2 && STAGES <= 4 && (STAGES - 1) * LOADS <= 63, "vmcnt range");
   static_assert(THREADS <= 1024, "workgroup size");
-  static_assert(KS == 1 || (KS == 2 && BN % 2 == 0 && MT * NT <= LDS_DOUBLES),
-                "two k-groups share the column blocks of the epilogue through the LDS ring");
+  static_assert(KS == 1 || (KS == 2 && BN % 2 == 0 && MT * NT <= LDS_DOUBLES) ||
+                    (KS == 4 && BM * BN == 4 && WAVES * 4 * 256 <= LDS_DOUBLES),
+                "k-groups share the blocks of the epilogue through the LDS ring");
 };
 
 __device__ __forceinline__ int ring_swz(int row) { return (row & 7) ^ ((row >> 3) & 1); }
@@ -1083,7 +1084,7 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
   // Two k-groups: group g keeps column blocks [g BN/2, (g+1) BN/2) of its wave's tile and hands
   // the others to the group that keeps them, through the (drained) LDS ring. Each entry becomes
   // (group 0's sum) + (group 1's sum), the same value whichever group adds it.
-  constexpr int kHalf = R::BN / R::KS;
+  constexpr int kHalf = R::KS == 4 ? 1 : R::BN / R::KS;  // (four groups return before its use)
   if constexpr (R::KS == 2) {
     constexpr int kPer = R::BM * kHalf * 4 * 64;  // doubles one wave hands over
     ring_barrier();  // every wave is past its last fragment read; no direct load is in flight
@@ -1123,6 +1124,46 @@ __device__ __forceinline__ void ring_tile(const GemmArgs& g, int tm, int tn, dou
     return col0 + wave_n * R::WN +
            (TB ? 32 * (bj2 >> 1) + 2 * (lq + 4 * r) + (bj2 & 1) : 16 * bj2 + lq + 4 * r);
   };
+
+  // Four k-groups: every wave hands all four of its blocks to the LDS ring; group g then owns
+  // block (g / BN, g % BN) of its wave's tile, adds the four groups' partial sums in group order
+  // (the same value whichever group adds it) and writes that block of C.
+  if constexpr (R::KS == 4) {
+    ring_barrier();  // every wave is past its last fragment read; no direct load is in flight
+    double* mine = smem + (grp * R::WAVES_G + wave) * 4 * 256;
+#pragma unroll
+    for (int bi = 0; bi < R::BM; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < R::BN; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mine[((bi * R::BN + bj) * 4 + r) * 64 + lane] = acc[bi][bj][r];
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    ring_barrier();
+    const int bi_o = grp / R::BN, bj_o = grp % R::BN;
+    double sum[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = ((grp * 4 + r) * 64) + lane;  // block grp of each group's wave slot
+      sum[r] = ((smem[(0 * R::WAVES_G + wave) * 1024 + e] + smem[(1 * R::WAVES_G + wave) * 1024 + e]) +
+                smem[(2 * R::WAVES_G + wave) * 1024 + e]) + smem[(3 * R::WAVES_G + wave) * 1024 + e];
+    }
+    const int64_t i = row_of(bi_o);
+    double cb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = col_of(bj_o, r);
+      cb[r] = (beta != 0.0 && i < g.m && j < g.n) ? g.C[j * g.ldc + i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = col_of(bj_o, r);
+      if (i < g.m && j < g.n) {
+        const double v = alpha * sum[r];
+        g.C[j * g.ldc + i] = (beta != 0.0) ? fma(beta, cb[r], v) : v;
+      }
+    }
+    return;
+  }
   // A tile wholly inside C (outside the triangle masking) takes a path with no condition on any
   // load or store: under per-element conditions the compiler cannot count the memory operations
   // in flight and waits for each store to complete before the next one goes out.
@@ -1277,6 +1318,8 @@ using Ring128x256t = RingCfg<128, 256, 128, 32, 3, 2, 1>;  // 8 waves of 128x32 
 using Ring64k2 = RingCfg<64, 64, 32, 32, 4, 2, 1, 2>;
 // Two k-groups of 4 waves of 64x64 on a 128x128 tile, 2 stages (139 KB of LDS).
 using Ring128k2 = RingCfg<128, 128, 64, 64, 2, 2, 1, 2>;
+// Four k-groups of 4 waves of 32x32 on a 64x64 tile, 2 ring slots of four panels (128 KB of LDS).
+using Ring64k4 = RingCfg<64, 64, 32, 32, 2, 4, 1, 4>;
 
 typedef void (*KernelFn)(GemmArgs, int, int);
 
@@ -1366,6 +1409,7 @@ const Variant kVariants[] = {
     make_ring_variant<Ring64k2>("ringk2_f64_64x64x16_w32x32_s4", 0),
     // one round of 128x128 tiles: 2048^3 and 2048^2 x 8192 at 69.6-73.7 TFLOP/s
     make_ring_variant<Ring128k2>("ringk2_f64_128x128x16_w64x64_s2", Eff(946, 946, 946, 946)),
+    make_ring_variant<Ring64k4>("ringk4_f64_64x64x16_w32x32_s2", 0),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1612,12 +1656,22 @@ int pick_by_cost(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double* cost
 
 // A grid of at most one workgroup per CU leaves each SIMD one wave of a one-group tile; the
 // k-split configuration of the same tile runs two per SIMD there (measured at 1024^3: 8% faster;
-// with two or more tiles per CU the one-group form is as fast or faster).
+// with two or more tiles per CU the one-group form is as fast or faster). Four groups (four waves
+// per SIMD, two ring slots) pay off only on long k: on 64x64 tiles 2-5% faster than two groups at
+// k = 4096 and 8192, the same at 2048, 1-5% slower at k = 300 to 1024.
+constexpr int64_t kFourGroupsK = 2048;
+
 int with_k_split(int v, int64_t m, int64_t n, int64_t k) {
   const Variant& b = kVariants[v];
   if (k > kShortK && b.ks == 1 && ceil_div(m, b.mt) * ceil_div(n, b.nt) <= kCUs) {
-    for (int w = 0; w < kNumVariants; ++w)
-      if (kVariants[w].ks == 2 && kVariants[w].mt == b.mt && kVariants[w].nt == b.nt) return w;
+    int two = -1, four = -1;
+    for (int w = 0; w < kNumVariants; ++w) {
+      if (kVariants[w].mt != b.mt || kVariants[w].nt != b.nt) continue;
+      if (kVariants[w].ks == 2) two = w;
+      if (kVariants[w].ks == 4) four = w;
+    }
+    if (four >= 0 && k > kFourGroupsK) return four;
+    if (two >= 0) return two;
   }
   return v;
 }

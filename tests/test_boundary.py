@@ -199,16 +199,21 @@ def test_every_variant_is_reachable():
 
 def test_single_round_grids_take_the_k_split_tile():
     """A grid of at most one 64x64 tile per CU (256 CUs) with k above the short-k bound runs the
-    k-split configuration of that tile; more tiles or short k keep the one-group choice. One round
-    of 128x128 tiles that fills most of the GPU runs the k-split 128x128 tile."""
+    k-split configuration of that tile: two groups up to k = 2048, four beyond; more tiles or short
+    k keep the one-group choice. One round of 128x128 tiles that fills most of the GPU runs the
+    k-split 128x128 tile."""
     name = mdg.mdg_variant_name
     for ta in "NT":
         for tb in "NT":
-            for m, n, k in ((1024, 1024, 1024), (1000, 1000, 300), (512, 2048, 4096)):
-                assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
+            for m, n, k in ((1024, 1024, 1024), (1000, 1000, 300), (1024, 1024, 2048)):
+                assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)) == \
+                    "ringk2_f64_64x64x16_w32x32_s4"
+            for m, n, k in ((512, 2048, 4096), (1024, 1024, 2049), (1024, 1024, 8192)):
+                assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)) == \
+                    "ringk4_f64_64x64x16_w32x32_s2"
             for m, n, k in ((1024, 1024, 256), (1089, 1024, 1024), (1536, 1536, 2048),
                             (8192, 8192, 8192)):
-                assert not name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk2_")
+                assert not name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)).startswith("ringk")
             for m, n, k in ((2048, 2048, 2048), (2048, 2048, 8192), (642, 4924, 4096)):
                 assert name(mdg.mdg_select_variant(ta, tb, m, n, k, 1.0, 1.0)) == \
                     "ringk2_f64_128x128x16_w64x64_s2"

@@ -234,14 +234,14 @@ def test_variant_family_agrees_bitwise_on_float_data(trans, family):
 
 @pytest.mark.parametrize("trans", TRANS)
 def test_ksplit_k_tails_integer_bit_exact(trans):
-    """The k-split ring configurations (two wave groups taking alternate 16-deep panels, summed in
-    a fixed order at the end): every k around the 32-deep ring slot (group 1 with a full, partial or
-    empty last panel, k below one panel) is exact on integer data, and a second call returns the
-    same bits on float data."""
+    """The k-split ring configurations (two or four wave groups taking alternate 16-deep panels,
+    summed in a fixed order at the end): every k around the 32- or 64-deep ring slot (later groups
+    with a full, partial or empty last panel, k below one panel) is exact on integer data, and a
+    second call returns the same bits on float data."""
     import paper_1609_00076_amd as mdg
-    ks2 = [x for x in VARIANTS[1:] if mdg.mdg_variant_name(x).startswith("ringk2_")]
-    assert len(ks2) == 2
-    for v in ks2:
+    ksplit = [x for x in VARIANTS[1:] if mdg.mdg_variant_name(x).startswith("ringk")]
+    assert len(ksplit) == 3
+    for v in ksplit:
         for k in (1, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64, 65, 96, 97, 130):
             p = synth.problem(21, k, trans[0], trans[1], 70, 131, k, ld_rule=_pad3, dist="int")
             check_parity(p, 1.5, -0.5, v, exact=True)

@@ -155,27 +155,36 @@ def traffic_from(dirs, copy_bytes, mdg):
 
 def blas3_traffic_from(dirs, copy_bytes, n=8192):
     """Write BLAS3_TRAFFIC_FILE from four rocprofv3 --pmc runs as in traffic_from, the first two
-    of `bench.py --workload blas3 --steps 1 --warmup 0 --cpu-budget 0`: the dsyrk launch's bytes."""
+    of `bench.py --workload blas3 --steps 1 --warmup 0 --cpu-budget 0`: the bytes of the dsyrk
+    call's launches (the triangle-kernel launch and the n / 1024 - 1 GEMM launches before it)."""
     f_dir, w_dir, cf_dir, cw_dir = dirs
     def scale(run_dir, counter):
         vals = [v for _, (name, v) in sorted(read_counter(run_dir, counter).items())]
         return copy_bytes / (sorted(vals[-3:])[1] * 1024.0)
     fs, ws = scale(cf_dir, "FETCH_SIZE"), scale(cw_dir, "WRITE_SIZE")
+    gemms = n // 1024 - 1  # GEMM launches of the call before its triangle launch
     got = {}
     for counter, d, sc in (("FETCH_SIZE", f_dir, fs), ("WRITE_SIZE", w_dir, ws)):
-        vals = [v for _, (name, v) in sorted(read_counter(d, counter).items())
-                if "dsyrk_ring_kernel" in name]
-        if not vals:
+        rows = sorted(read_counter(d, counter).items())
+        first = [i for i, (_, (name, _)) in enumerate(rows) if "dsyrk_ring_kernel" in name]
+        if not first:
             raise SystemExit(f"{counter}: no dsyrk dispatch in {d}")
-        got[counter] = (sum(vals) / len(vals) * 1024.0 * sc, len(vals))
+        i = first[0]
+        call = rows[i - gemms:i + 1]
+        if len(call) != gemms + 1 or not all("dgemm" in nm for _, (nm, _) in call[:-1]):
+            raise SystemExit(f"{counter}: the {gemms} GEMM dispatches before the dsyrk one are missing")
+        got[counter] = (sum(v for _, (_, v) in call) * 1024.0 * sc,
+                        call[-1][1][1] * 1024.0 * sc, len(call))
     alg = 8.0 * (n * n + n * (n + 1))  # A read once, the triangle of C read and written
     out = {"source_sha": source_hash(), "n": n,
-           "dsyrk_bytes_per_launch": got["FETCH_SIZE"][0] + got["WRITE_SIZE"][0],
+           "dsyrk_call_bytes": got["FETCH_SIZE"][0] + got["WRITE_SIZE"][0],
            "fetch_bytes": got["FETCH_SIZE"][0], "write_bytes": got["WRITE_SIZE"][0],
-           "launches": [got["FETCH_SIZE"][1], got["WRITE_SIZE"][1]],
+           "triangle_launch_bytes": got["FETCH_SIZE"][1] + got["WRITE_SIZE"][1],
+           "launches": got["FETCH_SIZE"][2],
            "fetch_scale": fs, "write_scale": ws, "algorithmic_bytes": alg,
-           "note": f"dsyrk L N n=k={n} launch: FETCH_SIZE + WRITE_SIZE (KiB x 1024) times the "
-                   "factors that map each counter's reading of a device copy to the bytes it moves"}
+           "note": f"dsyrk L N n=k={n} call ({gemms} GEMM launches, then the triangle launch over "
+                   "the diagonal blocks): FETCH_SIZE + WRITE_SIZE (KiB x 1024) times the factors "
+                   "that map each counter's reading of a device copy to the bytes it moves"}
     with open(BLAS3_TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -859,7 +868,8 @@ def blas3_workload(args, torch, mdg):
         tf = fl / (med * 1e-3) / 1e12
         by_op[name] = {"ms": round(med, 3), "tflops": round(tf, 2),
                        "frac_of_peak": round(tf / PEAK_FP64_MFMA_TFLOPS, 4), "flops": fl}
-    # The dsyrk call is one kernel launch: its roofline is that launch's.
+    # The roofline is the dsyrk call's: at n = 8192 the GEMMs between its diagonal blocks (seven
+    # launches) and one launch of the triangle kernel over the eight diagonal blocks.
     syrk_ms = by_op["dsyrk"]["ms"]
     achieved = ops["dsyrk"][1] / (syrk_ms * 1e-3) / 1e12
     cpu = None
@@ -868,14 +878,14 @@ def blas3_workload(args, torch, mdg):
         v, cores, desc = blas3_cpu_baseline(hA, hT, hB, n, args.cpu_budget)
         cpu = {"value": v, "unit": "TFLOP/s", "cores": cores, "kind": "oracle", "sample": desc}
     vid = mdg.mdg_dsyrk_select_variant("L", "N", n, n)
-    # HBM bytes of the dsyrk launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), valid
-    # only if taken on this kernel source.
+    # HBM bytes of the dsyrk call's launches (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated),
+    # valid only if taken on this kernel source.
     traffic = None
     if os.path.exists(BLAS3_TRAFFIC_FILE):
         try:
             t = json.load(open(BLAS3_TRAFFIC_FILE))
             if t.get("source_sha") == source_hash() and t.get("n") == n:
-                traffic = t.get("dsyrk_bytes_per_launch")
+                traffic = t.get("dsyrk_call_bytes")
         except (OSError, ValueError):
             traffic = None
     out = {
@@ -889,10 +899,13 @@ def blas3_workload(args, torch, mdg):
                 "magnitude in [1,2), off-diagonal U[-1,1)/n); resident in HBM before timing",
         "config": {"workload": f"dsyrk L N n=k={n}; dtrmm and dtrsm L L N N m=n={n}; ld = rows; "
                                "alpha = beta = 1", "flops_per_step": step_flops, "by_op": by_op},
-        "roofline": {"bound": "mfma", "kernel": f"dsyrk ring kernel ({mdg.mdg_variant_name(vid)}, lower)",
+        "roofline": {"bound": "mfma",
+                     "kernel": f"dsyrk call: {n // 1024 - 1} GEMM launches between the diagonal "
+                               f"blocks, then the triangle kernel ({mdg.mdg_variant_name(vid)}, "
+                               f"lower) over {n // 1024} diagonal blocks of order 1024",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "avg_launch_ms": syrk_ms,
-                     "launches": args.steps, "traffic": traffic,
+                     "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "avg_call_ms": syrk_ms,
+                     "calls": args.steps, "traffic": traffic,
                      "algorithmic_bytes": 8.0 * (n * n + n * (n + 1))},
         "cpu_baseline": cpu,
     }

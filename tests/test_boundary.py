@@ -251,8 +251,12 @@ def test_dsyrk_quick_returns_and_refusals():
 
 
 def test_dsyrk_choice_is_host_logic():
+    # n = 8192 splits: the triangle launch covers eight diagonal blocks of order 1024, on 64x64
+    # tiles; n = 6144 is one launch over the whole triangle, on 128x64 tiles
     vid = mdg.mdg_dsyrk_select_variant("L", "N", 8192, 8192)
-    assert mdg.mdg_variant_name(vid) == "ring_f64_128x64x16_w32x32_s3_il"  # the measured best
+    assert mdg.mdg_variant_name(vid) == "ring_f64_64x64x16_w32x32_s3_il"
+    vid = mdg.mdg_dsyrk_select_variant("L", "N", 6144, 6144)
+    assert mdg.mdg_variant_name(vid) == "ring_f64_128x64x16_w32x32_s3_il"
     for uplo, trans in (("U", "N"), ("L", "T"), ("U", "T")):
         assert mdg.mdg_dsyrk_select_variant(uplo, trans, 8192, 8192) >= 0
     assert mdg.mdg_dsyrk_select_variant("X", "N", 10, 10) == -2

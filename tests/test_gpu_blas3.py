@@ -285,6 +285,38 @@ def test_syrk_no_product_and_refusals(uplo):
     assert mdg.mdg_dsyrk(uplo, "T", n, 4, 1.0, to_dev(A), 3, 0.5, None, ldc) == 7
 
 
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("trans", "NT")
+def test_syrk_split_against_oracle(uplo, trans):
+    """n = 4096 with the automatic choice: the rectangles between diagonal blocks of order 1024 as
+    GEMMs (one 2048^2, two 1024^2), then one launch over the four diagonal blocks; exact on integer
+    data, within 1e-13 of |alpha| |op(A)||op(A)^T| + |beta||C| on uniform data, the other triangle
+    and the padding untouched."""
+    n, k = 4096, 40
+    base = 700 + 10 * "LU".index(uplo) + 4 * "NT".index(trans)
+    for case, (dist, alpha, beta) in enumerate((("int", 1.5, -0.5), ("uniform", -1.25, 0.75))):
+        A, lda, C, ldc, other = _syrk_case(base + case, uplo, trans, n, k, dist)
+        ref = C.copy()
+        assert oracle.dsyrk(uplo, trans, n, k, alpha, A, lda, beta, ref, ldc) == 0
+        print(f"[syrk split] {uplo}{trans} {dist}", flush=True)
+        st, got = _run_syrk(-1, uplo, trans, n, k, alpha, A, lda, beta, C, ldc)
+        assert st == 0
+        g, r = synth.view2d(got, n, n, ldc), synth.view2d(ref, n, n, ldc)
+        C0 = synth.view2d(C, n, n, ldc)
+        assert np.array_equal(g[other].view(np.uint64), C0[other].view(np.uint64))
+        assert _pad_same(got, C, n, ldc)
+        tri = ~other
+        if dist == "int":
+            assert np.array_equal(g[tri], r[tri])
+        else:
+            ra, ca = (n, k) if trans == "N" else (k, n)
+            opA = synth.view2d(A, ra, ca, lda)
+            opA = opA if trans == "N" else opA.T
+            D = abs(alpha) * (np.abs(opA) @ np.abs(opA).T) + abs(beta) * np.abs(np.where(other, 0.0, C0))
+            err = np.abs(g[tri] - r[tri])
+            assert np.all(err <= TOL * D[tri]), float(np.max(err / np.maximum(D[tri], 1e-300)))
+
+
 # ---- full size: the benchmark's shapes and launch configuration, checked on samples ---------------
 
 BIG = 8192

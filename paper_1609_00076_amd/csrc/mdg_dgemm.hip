@@ -1419,7 +1419,8 @@ const Variant kVariants[] = {
     make_ring_variant<Ring128x256t>("ring_f64_128x256x16_w128x32_s3_il", Eff(947, 938, 936, 946)),
     make_wave_variant("wave_f64_64x64x8_w32x32", 0),
     make_ring_variant<Ring64k2>("ringk2_f64_64x64x16_w32x32_s4", 0),
-    // one round of 128x128 tiles: 2048^3 and 2048^2 x 8192 at 69.6-73.7 TFLOP/s
+    // one round of 128x128 tiles: 2048^3 at 63.7-70.5 and 2048^2 x 8192 at 72.5-73.7 TFLOP/s, 3-5%
+    // above the one-group 128x128 and 128x64 tiles
     make_ring_variant<Ring128k2>("ringk2_f64_128x128x16_w64x64_s2", Eff(946, 946, 946, 946)),
     make_ring_variant<Ring64k4>("ringk4_f64_64x64x16_w32x32_s2", 0),
 };
@@ -1642,7 +1643,7 @@ double tile_cost(const Variant& var, bool ta, bool tb, int64_t m, int64_t n, int
   const int eff = short_k ? var.short_k_permil : var.eff_permil[ta][tb];
   if (eff <= 0) return -1.0;
   const int64_t tiles = ceil_div(m, var.mt) * ceil_div(n, var.nt);
-  if (var.ks != 1 && tiles > kCUs) return -1.0;  // two k-groups pay off on one round only
+  if (var.ks != 1 && tiles > kCUs) return -1.0;  // k-split tiles pay off on one round only
   const int64_t per_cu = ceil_div(tiles, kCUs);
   const int64_t resident = per_cu < var.wgs_per_cu ? per_cu : var.wgs_per_cu;
   const double occupancy = std::cbrt((double)resident / var.wgs_per_cu);

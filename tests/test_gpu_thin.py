@@ -146,3 +146,59 @@ def test_split_plan_whole_matrix_against_the_oracle():
     assert v >= 0 and m0 < m and n0 < n, (v, m0, n0)
     p = synth.problem(39, 0, trans[0], trans[1], m, n, k, ld_rule=_pad3, dist="int")
     check_parity(p, -1.5, 2.0, exact=True)
+
+
+def test_split_paths_graph_replay_matches_eager():
+    """The multi-launch paths (a dgemm split into a tiled block and one thin launch, a thin-only
+    dgemm, a dsyrk split into GEMMs and one launch over its diagonal blocks) captured in one graph
+    on torch's stream: every replay, with eager work and synchronizations between replays, gives
+    the eager results bit for bit."""
+    import torch
+    import paper_1609_00076_amd as mdg
+    from gpu_util import to_dev
+    m, n, k = 1030, 2000, 300
+    assert _plan("TN", m, n, k)[1:] == (1024, 1984)
+    assert _plan("NN", 5, 3000, 513)[0] == -1
+    p1 = synth.problem(40, 0, "T", "N", m, n, k, ld_rule=_pad3)
+    p2 = synth.problem(40, 1, "N", "N", 5, 3000, 513, ld_rule=_pad3)
+    ns, ks = 4096, 40
+    hA = synth.matrix(synth.seed_for(40, 2, 0), ns, ks, ns, "uniform")
+    hC = synth.matrix(synth.seed_for(40, 2, 1), ns, ns, ns, "uniform")
+    d1 = [to_dev(p1[x]) for x in "ABC"]
+    d2 = [to_dev(p2[x]) for x in "ABC"]
+    dA, dC = to_dev(hA), to_dev(hC)
+    inits = [(d1[2], d1[2].clone()), (d2[2], d2[2].clone()), (dC, dC.clone())]
+
+    def calls():
+        assert mdg.mdg_dgemm("T", "N", m, n, k, 1.25, d1[0], p1["lda"], d1[1], p1["ldb"], -0.5,
+                             d1[2], p1["ldc"]) == 0
+        assert mdg.mdg_dgemm("N", "N", 5, 3000, 513, 0.75, d2[0], p2["lda"], d2[1], p2["ldb"], 1.5,
+                             d2[2], p2["ldc"]) == 0
+        assert mdg.mdg_dsyrk("L", "N", ns, ks, 0.5, dA, ns, 1.5, dC, ns) == 0
+
+    def reset():
+        for x, x0 in inits:
+            x.copy_(x0)
+
+    calls()  # eager results
+    torch.cuda.synchronize()
+    want = [x.clone() for x, _ in inits]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # torch's warm-up-before-capture on a side stream
+        reset()
+        calls()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    reset()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls()
+    for rep in range(3):
+        reset()  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for (got, _), ref in zip(inits, want):
+            assert torch.equal(got.view(torch.int64), ref.view(torch.int64)), f"replay {rep}"

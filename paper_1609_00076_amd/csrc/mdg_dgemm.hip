@@ -1986,8 +1986,13 @@ int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, i
   const bool ta = is_trans(transa), tb = is_trans(transb);
   DgemmPlan pl =
       (variant == MDG_VARIANT_AUTO) ? plan_dgemm(ta, tb, m, n, k) : DgemmPlan{variant, m, n};
-  if ((pl.m0 < m || pl.n0 < n) && std::max(lda, ldb) > kThinMaxLd)
-    pl = DgemmPlan{pick_variant(ta, tb, m, n, k), m, n};  // offsets beyond the thin kernel's
+  // The thin launch's workgroups: 16 outputs each along n (fringe rows) and along m0 (fringe
+  // columns). Offsets or a grid beyond the thin kernel's keep the whole product on the tiles.
+  const int64_t thin_blocks = (pl.m0 < m ? ceil_div(n, kThinL) : 0) +
+                              (pl.n0 < n && pl.m0 > 0 ? ceil_div(pl.m0, kThinL) : 0);
+  if (thin_blocks > 0 &&
+      (std::max(lda, ldb) > kThinMaxLd || thin_blocks > (int64_t)INT32_MAX / 1024))
+    pl = DgemmPlan{pick_variant(ta, tb, m, n, k), m, n};
   if (pl.vid >= 0) {
     const Variant& v = kVariants[pl.vid];
     if (ceil_div(pl.m0, v.mt) * ceil_div(pl.n0, v.nt) > (int64_t)INT32_MAX / 1024)
@@ -1995,7 +2000,6 @@ int dgemm_prepare(int variant, char transa, char transb, int64_t m, int64_t n, i
     if (!panel_offsets_fit(ta, tb, v.mt, v.nt, v.kt, pl.m0, pl.n0, k, lda, ldb))
       return MDG_ERR_SIZE;
   }
-  if (ceil_div(m, kThinL) + ceil_div(n, kThinL) > (int64_t)INT32_MAX / 1024) return MDG_ERR_SIZE;
   *plan = pl;
   return MDG_SUCCESS;
 }

@@ -125,6 +125,11 @@ def test_leading_dimension_offset_guard_is_host_side_and_exact():
     # guard lets it through (here the call then stops at the device check: no GPU)
     st = mdg.mdg_dgemm("T", "T", 1, 1, 1, 1.0, fake, big, fake, big, 0.0, fake, 1)
     assert st != -4 and st < 0
+    # a C of 40 million rows and one column: too many thin-kernel workgroups for one launch, so
+    # the product stays on the tiles, whose grid fits (the call then stops at the device check)
+    st = mdg.mdg_dgemm("N", "N", 40_000_000, 1, 1, 1.0, fake, 40_000_000, fake, 1, 0.0, fake,
+                       40_000_000)
+    assert st != -4 and st < 0
     # alpha = 0: A and B are not read, so their leading dimensions do not matter
     st = mdg.mdg_dgemm("T", "N", 300, 64, 64, 0.0, fake, big, fake, 64, 1.0, fake, 300)
     assert st == 0  # quick return (beta = 1)

@@ -353,9 +353,9 @@ int mdg_dgemm_grouped(const void *device_plan, int64_t num_tiles, int grid, void
  *
  * uplo 'L' ('l'): the lower triangle (i >= j) is read and written; 'U': the upper (i <= j). The
  * other triangle is neither read nor written. One launch of the GEMM's ring kernels over the
- * tiles that meet the triangle, the epilogue masked to it; for n = 1024 * 2^j >= 4096 the
- * rectangles between diagonal blocks of order 1024 are computed first as GEMMs (mdg_dgemm), and
- * the one launch covers the diagonal blocks only. Checks: 1 uplo, 2 trans, 3 n < 0,
+ * tiles that meet the triangle, the epilogue masked to it; for n = 1024 * 2^j >= 4096 and
+ * k >= 2048 the rectangles between diagonal blocks of order 1024 are computed first as GEMMs
+ * (mdg_dgemm), and the one launch covers the diagonal blocks only. Checks: 1 uplo, 2 trans, 3 n < 0,
  * 4 k < 0, 6 A == NULL where read, 7 lda < max(1, rows of stored A), 9 C == NULL where touched,
  * 10 ldc < max(1, n). alpha == 0 or k == 0: A is not read and the triangle becomes beta*C
  * (beta == 0 writes zeros without reading C); n == 0, or that case with beta == 1: nothing is
@@ -374,8 +374,8 @@ int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, doubl
                  const double *A, int64_t lda, double beta, double *C, int64_t ldc, void *stream);
 
 /* The GEMM variant id of mdg_dsyrk's triangle launch for a product of this shape (for
- * n = 1024 * 2^j >= 4096 the launch over the diagonal blocks; host only), or MDG_ERR_VARIANT for
- * invalid flags or sizes. */
+ * n = 1024 * 2^j >= 4096 and k >= 2048 the launch over the diagonal blocks; host only), or
+ * MDG_ERR_VARIANT for invalid flags or sizes. */
 int mdg_dsyrk_select_variant(char uplo, char trans, int64_t n, int64_t k);
 
 /*

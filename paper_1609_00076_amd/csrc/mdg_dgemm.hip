@@ -1860,12 +1860,15 @@ int pick_syrk(int tri, bool ta, int64_t n, int64_t k, int only, int64_t batch = 
 // launch of the triangle kernel over all of them (blockIdx.y selects the block). Measured against
 // the single triangle launch, k = n: n = 8192 7.9 against 8.6 ms, n = 4096 1.11 against 1.13 ms;
 // at n = 6144 (six blocks, so rectangles of 2048 x 1024 and 3072 x 3072 that tile badly) 3.9
-// against 3.6 ms, hence the restriction to powers of two.
+// against 3.6 ms, hence the restriction to powers of two. With k < 2048 the GEMMs are short and
+// the extra launches cost more than they save (n = 8192: 3-18% slower at k = 40 to 1024, 1%
+// faster at 2048; n = 4096: the same at 2048).
 constexpr int64_t kSyrkSplitN = 4096;
+constexpr int64_t kSyrkSplitK = 2048;
 constexpr int64_t kSyrkLeaf = 1024;
 
-bool syrk_splits(int64_t n) {
-  if (n < kSyrkSplitN || n % kSyrkLeaf != 0) return false;
+bool syrk_splits(int64_t n, int64_t k) {
+  if (n < kSyrkSplitN || k < kSyrkSplitK || n % kSyrkLeaf != 0) return false;
   const int64_t p = n / kSyrkLeaf;
   return (p & (p - 1)) == 0;
 }
@@ -2114,10 +2117,10 @@ int mdg_dsyrk_ex(int variant, char uplo, char trans, int64_t n, int64_t k, doubl
   if (!touches_c) return MDG_SUCCESS;
   const int tri = is_lower(uplo) ? 1 : 2;
 
-  // Automatic calls on n = 1024 * 2^j >= 4096: the rectangles between diagonal blocks as GEMMs,
-  // then one launch over the diagonal blocks (syrk_splits); otherwise one launch over the whole
-  // triangle.
-  const bool split = !no_product && variant == MDG_VARIANT_AUTO && syrk_splits(n);
+  // Automatic calls on n = 1024 * 2^j >= 4096 with k >= 2048: the rectangles between diagonal
+  // blocks as GEMMs, then one launch over the diagonal blocks (syrk_splits); otherwise one launch
+  // over the whole triangle.
+  const bool split = !no_product && variant == MDG_VARIANT_AUTO && syrk_splits(n, k);
   const int64_t leaf = split ? kSyrkLeaf : n;
   const int64_t blocks = split ? ceil_div(n, kSyrkLeaf) : 1;
   std::vector<SyrkRect> rects;
@@ -2178,7 +2181,7 @@ int mdg_dsyrk_select_variant(char uplo, char trans, int64_t n, int64_t k) {
   if ((!is_lower(uplo) && !is_upper(uplo)) || (!is_notrans(trans) && !is_trans(trans)) ||
       n < 0 || k < 0)
     return MDG_ERR_VARIANT;
-  const bool split = k > 0 && syrk_splits(n);
+  const bool split = syrk_splits(n, k);
   const int s_idx = pick_syrk(is_lower(uplo) ? 1 : 2, is_trans(trans), split ? kSyrkLeaf : n, k, -1,
                               split ? ceil_div(n, kSyrkLeaf) : 1);
   return s_idx < 0 ? MDG_ERR_VARIANT : variant_by_name(kSyrkVariants[s_idx].name);

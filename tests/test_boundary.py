@@ -262,6 +262,12 @@ def test_dsyrk_choice_is_host_logic():
     assert mdg.mdg_variant_name(vid) == "ring_f64_64x64x16_w32x32_s3_il"
     vid = mdg.mdg_dsyrk_select_variant("L", "N", 6144, 6144)
     assert mdg.mdg_variant_name(vid) == "ring_f64_128x64x16_w32x32_s3_il"
+    # the split needs k >= 2048: below it n = 8192 is one launch over the whole triangle
+    assert mdg.mdg_variant_name(mdg.mdg_dsyrk_select_variant("L", "N", 8192, 2048)) == \
+        "ring_f64_64x64x16_w32x32_s3_il"
+    assert mdg.mdg_variant_name(mdg.mdg_dsyrk_select_variant("L", "N", 8192, 2047)) == \
+        "ring_f64_128x64x16_w32x32_s3_il"
+
     for uplo, trans in (("U", "N"), ("L", "T"), ("U", "T")):
         assert mdg.mdg_dsyrk_select_variant(uplo, trans, 8192, 8192) >= 0
     assert mdg.mdg_dsyrk_select_variant("X", "N", 10, 10) == -2
